@@ -1,0 +1,238 @@
+#!/usr/bin/env python3
+"""Throughput of the least-misfit gridding / FFT / degridding path on one MI355X.
+
+One step is one pass of the whole hot path over the workload's visibilities:
+build the uv plan (coordinates -> tap cells and offsets in FP64, counting
+sort by uv tile), make the dirty image (grid, inverse FFT, correct, crop) and
+predict visibilities from that image (correct, pad, forward FFT, degrid).
+The table (host LM optimisation, once per W/x0/size) is built before timing.
+
+Default workload: 16,777,152 visibilities from a synthetic 64-antenna array
+(2,016 baselines x 8,322 hour angles, 50-source sky) on a 4096^2 grid, W = 7,
+x0 = 0.25, 300-entry table with cubic interpolation, FP32 data.
+
+Prints ONE JSON line. Per-kernel times come from HIP events the library
+records around its own launches on the launch stream (lmg_trace_*).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+METRIC = "visibilities/s gridded+degridded at W=7, 4096² grid (HBM GB/s % peak)"
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(HERE, "paper_1906_07102_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(name: str, nvis: int, N: int, M: int, cs: int) -> float:
+    """Bytes the method must move per launch of each kernel (counted per visibility / per grid cell).
+
+    uv 16 B, visibility cs B, weight 4 B per visibility; grids and images
+    counted once per read or write.
+    """
+    rs = cs // 2
+    return {
+        "plan_count": 16.0 * nvis,
+        "plan_scan": 0.0,
+        "plan_scatter": 16.0 * nvis,
+        "grid_items": (16.0 + cs + 4.0) * nvis,
+        "assemble": float(N) * N * cs,
+        "degrid_items": (16.0 + cs) * nvis + float(N) * N * cs,
+        "fft_rows_inverse": float(N) * N * cs + float(M) * N * cs,
+        "fft_cols_inverse_correct_crop": float(M) * N * cs + float(M) * M * cs + 0 * rs,
+        "fft_rows_forward_correct_pad": float(M) * M * cs + float(N) * M * cs,
+        "fft_cols_forward": float(N) * M * cs + float(N) * N * cs,
+    }.get(name, 0.0)
+
+
+def load_traffic(kernel: str, nvis: int):
+    """Counter-measured HBM bytes per launch from profiles/, if taken on the current kernel sources."""
+    path = os.path.join(HERE, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != kernel_source_hash() or d.get("nvis") != nvis:
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(case, nvis_sample: int):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to visibilities/s of a whole step."""
+    from oracle import imaging as im
+    from oracle import lmtable as lt
+    tab, h = lt.make_table(case.W, case.x0, case.table_size, case.degree)
+    hp = lt.correction(h, case.W, case.x0, case.N)
+    uv = case.uv[:nvis_sample]
+    vis = case.vis[:nvis_sample].astype(np.complex128)
+    t0 = time.perf_counter()
+    G = im.grid(uv, vis, None, case.N, tab)
+    t1 = time.perf_counter()
+    img = im.dirty_from_grid(G, hp, case.x0)
+    t2 = time.perf_counter()
+    Gp = im.grid_from_image(img, hp, case.N, case.x0)
+    t3 = time.perf_counter()
+    im.degrid(uv, Gp, tab)
+    t4 = time.perf_counter()
+    per_vis = ((t1 - t0) + (t4 - t3)) / nvis_sample
+    step = per_vis * len(case.uv) + (t2 - t1) + (t3 - t2)
+    return {
+        "value": len(case.uv) / step,
+        "unit": "visibilities/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"FP64 NumPy oracle: grid + degrid of the first {nvis_sample} visibilities "
+                   f"({(t1 - t0) + (t4 - t3):.1f} s) and one inverse + one forward {case.N}^2 radix-2 FFT with "
+                   f"correction ({(t2 - t1) + (t3 - t2):.1f} s), scaled to the full {len(case.uv)}-visibility step"),
+        "seconds": round(t4 - t0, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["f32", "kahan", "f64"], default="f32")
+    ap.add_argument("--workload", choices=["array-16m-4096", "array-1m-2048"], default="array-16m-4096")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 19)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
+              f"(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    sys.path.insert(0, HERE)
+    import paper_1906_07102_amd as lmg
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = {"f32": lmg.F32, "kahan": lmg.F32_KAHAN, "f64": lmg.F64}[args.precision]
+    cdt = torch.complex128 if prec == lmg.F64 else torch.complex64
+    cs = 16 if prec == lmg.F64 else 8
+    t_in = time.perf_counter()
+    case = synth.array_16m_case(with_vis=True, device="cuda") if args.workload == "array-16m-4096" \
+        else synth.array_1m_case(with_vis=True, device="cuda")
+    N, W, nvis = case.N, case.W, len(case.uv)
+    M = int(round(2 * case.x0 * N))
+    uv = torch.from_numpy(case.uv).to(dev)
+    vis = torch.from_numpy(case.vis).to(dev, cdt)
+    w = torch.ones(nvis, dtype=torch.float32, device=dev)
+    t_inputs = time.perf_counter() - t_in
+    t_tab = time.perf_counter()
+    table = lmg.Table.create(W, case.x0, case.table_size, case.degree)
+    t_tab = time.perf_counter() - t_tab
+    print(f"# inputs {t_inputs:.1f}s, table {t_tab:.2f}s, nvis={nvis} N={N}", file=sys.stderr, flush=True)
+    img = torch.empty((M, M), dtype=cdt, device=dev)
+    vout = torch.empty(nvis, dtype=cdt, device=dev)
+
+    def step():
+        plan = lmg.Plan(table, N, uv, prec)
+        plan.make_dirty_image(vis, w, out=img)
+        plan.predict_visibilities(img, out=vout)
+        return plan
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lmg.trace_report()                       # discard anything recorded so far
+    lmg.trace_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    trace = lmg.trace_report()
+    lmg.trace_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    print(f"# step {ms:.3f} ms; plan {plan.info()}", file=sys.stderr, flush=True)
+
+    # Steady state with the plan reused (uv fixed, as in iterative imaging).
+    plan = lmg.Plan(table, N, uv, prec)
+    for _ in range(2):
+        plan.make_dirty_image(vis, w, out=img)
+        plan.predict_visibilities(img, out=vout)
+    torch.cuda.synchronize()
+    r0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.make_dirty_image(vis, w, out=img)
+        plan.predict_visibilities(img, out=vout)
+    torch.cuda.synchronize()
+    ms_reuse = (time.perf_counter() - r0) * 1e3 / args.steps
+
+    kernels = {}
+    for name, (n, tot) in trace.items():
+        avg = tot / n
+        ab = algorithmic_bytes(name, nvis, N, M, cs)
+        kernels[name] = {"launches": n, "avg_ms": round(avg, 5),
+                         "algorithmic_GBps": round(ab / (avg * 1e-3) / 1e9, 1) if ab else None}
+    dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
+    dom_avg_s = trace[dom][1] / trace[dom][0] * 1e-3
+    ab = algorithmic_bytes(dom, nvis, N, M, cs)
+    achieved = ab / dom_avg_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, nvis), "kernel": dom}
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": METRIC,
+        "value": nvis / (ms * 1e-3),
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "kahan": "f32", "f64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{case.name}: 64-antenna Gaussian array, 2016 baselines x {nvis // 2016} hour angles, "
+                         f"50-source sky; W={W}, x0={case.x0}, {case.table_size}-entry table, "
+                         f"degree {case.degree}; step = uv plan + dirty image + prediction"),
+            "nvis": nvis, "N": N, "W": W, "x0": case.x0, "table_size": case.table_size,
+            "degree": case.degree, "precision": args.precision, "accumulation": args.precision,
+        },
+        "roofline": roofline,
+        "kernels": kernels,
+        "value_plan_reused": nvis / (ms_reuse * 1e-3),
+        "ms_per_step_plan_reused": round(ms_reuse, 4),
+        "source_hash": kernel_source_hash(),
+    }
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(case, min(args.cpu_sample, nvis))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * lmgrid.h -- C ABI of the least-misfit gridding / degridding library (gfx950).
+ *
+ * Method: Ye, Gull, Tan & Nikolic, "Optimal gridding and degridding in radio
+ * interferometry imaging", MNRAS 2019. Equation numbers refer to the paper's
+ * main text.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns an lmg_status; nothing prints, throws or exits.
+ * - Pointers documented "device" must point to device memory of the current
+ *   HIP device; "host" pointers to host memory. The library never allocates
+ *   device memory: every device buffer, including workspaces, is owned by the
+ *   caller (for example a torch tensor) and must outlive the work enqueued on
+ *   it.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *   that take a stream only enqueue work and return; argument errors are
+ *   detected on the host before anything is enqueued.
+ * - uv coordinates are in grid cells (Sec. 2.1: u' = u L), an (nvis, 2)
+ *   float64 array with u in column 0 and v in column 1.
+ * - Grids are N x N, complex, stored centred: element [m + N/2][n + N/2]
+ *   holds G_{m,n} for m, n in [-N/2, N/2); rows follow v, columns follow u.
+ *   Taps that fall outside the grid wrap modulo N.
+ * - Images hold the pixels p, q in [-x0 N, x0 N) (x_p = p/N, y_q = q/N) as a
+ *   (2 x0 N) x (2 x0 N) complex array, element [q + x0 N][p + x0 N].
+ * - Complex data are interleaved (re, im): complex64 for LMG_F32 and
+ *   LMG_F32_KAHAN, complex128 for LMG_F64. Weights are float32 in all modes.
+ */
+#ifndef LMGRID_H
+#define LMGRID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LMG_OK = 0,
+    LMG_EINVAL = -1,      /* invalid argument (checked on the host, nothing enqueued) */
+    LMG_EWORKSPACE = -2,  /* workspace NULL or smaller than the size query returned */
+    LMG_EHIP = -3,        /* a HIP runtime call failed */
+    LMG_EDATA = -4,       /* non-finite uv coordinates were met (reported by lmg_plan_check) */
+    LMG_ENOTSUP = -5,     /* a valid request this build does not support (e.g. table too large) */
+    LMG_ENOCONV = -6      /* the table optimiser did not reach its tolerance */
+} lmg_status;
+
+typedef enum {
+    LMG_F32 = 0,        /* complex64 data, FP32 accumulation with LDS atomics */
+    LMG_F32_KAHAN = 1,  /* complex64 data, compensated (two-float) FP32 accumulation */
+    LMG_F64 = 2         /* complex128 data, FP64 throughout */
+} lmg_precision;
+
+/* ------------------------------------------------------------------ tables
+ * A table bundles the least-misfit correcting function h sampled at the
+ * N_g + 1 = 33 points x_i = i x0 / 32 of [0, x0] (App. A), the tabulated
+ * gridding function (App. E) and the interpolation degree (App. F).
+ *
+ * Offsets: a visibility at u spreads onto cells n_first .. n_first + W - 1
+ * with n_first = ceil(u - W/2) (the set S_k, Eq. 6). Its offset is
+ * delta = u - (n_first + ref), ref = (W-1)/2 for odd W and W/2 - 1 for even
+ * W, so delta lies in (-1/2, 1/2] (odd W) or (0, 1] (even W); tap j sits at
+ * distance t_j - delta with t_j = j - ref. The table holds, for each tap j,
+ * nodes C(t_j - delta_i) at delta_i = delta_lo + i / Ms, i = 0 .. Ms + degree
+ * (row-major W x (Ms + 1 + degree)); the `degree` nodes past the top of the
+ * interval continue the same smooth branch so that forward Newton stencils
+ * stay on it. Ms = table_size / W (a "300-entry" W = 3 table has 100 samples
+ * per cell, Abstract and Sec. 7).
+ * Interpolation: degree 0 takes the nearest node (ties to the upper one);
+ * degree d >= 1 the polynomial through nodes k .. k+d with
+ * delta_k <= delta < delta_{k+1} (App. F).
+ */
+typedef struct lmg_table lmg_table;
+
+/* Optimise h by Levenberg-Marquardt (App. A; initial guess h = 1 for W <= 4,
+ * h_{W-1}^2 / h_{W-2} otherwise, so W > 4 optimises the chain W = 3 .. W),
+ * solve the normal equations A C = B (Eqs. 17-19) by Cholesky at every node,
+ * and build the table. W in [1, 16]; x0 in (0, 0.5]; table_size >= W;
+ * degree in [0, 3]. Host only; takes milliseconds to a few seconds.
+ * On success *out owns a new table (free with lmg_table_destroy). */
+lmg_status lmg_table_create(int W, double x0, int table_size, int degree, lmg_table** out);
+
+/* Same, with h given (33 host doubles, h_coarse[0] is the scale and need not
+ * be 1): no optimisation, only the normal-equation solve (Eqs. 18-19). */
+lmg_status lmg_table_create_from_h(int W, double x0, int table_size, int degree,
+                                   const double* h_coarse, lmg_table** out);
+
+/* Same, with both h (33 host doubles) and the node values given
+ * (W * (Ms + 1 + degree) host doubles, layout above): the table is taken as
+ * data. Used to run the kernels on a table produced elsewhere. */
+lmg_status lmg_table_create_from_nodes(int W, double x0, int table_size, int degree,
+                                       const double* h_coarse, const double* nodes, lmg_table** out);
+
+/* Parameters of a table. Any output pointer may be NULL. */
+lmg_status lmg_table_info(const lmg_table* t, int* W, double* x0, int* Ms, int* degree,
+                          double* integrated_misfit);
+
+/* Copy out h (33 host doubles) and the nodes (W * (Ms + 1 + degree) host
+ * doubles). Either pointer may be NULL. */
+lmg_status lmg_table_export(const lmg_table* t, double* h_coarse, double* nodes);
+
+/* The exact least-misfit kernel (Eq. 18 solved at each offset): out[k*W + j]
+ * = C(t_j - delta[k]) for n host offsets (any real delta; the formula
+ * continues smoothly past the ends of the interval). */
+lmg_status lmg_table_kernel(const lmg_table* t, int n, const double* delta, double* out);
+
+/* Optimal correcting function (Eq. 12, equivalently Eq. 15) with the exact
+ * kernel at x_p = p / N, p = -N/2 .. N/2 - 1, into N host doubles. The nu
+ * integrals use 64-point Gauss-Legendre quadrature over one offset interval. */
+lmg_status lmg_correction(const lmg_table* t, int N, double* h_pix);
+
+/* Map error l(x) (Eq. 11) with the optimal correction at n host points x:
+ * ell_exact with the exact kernel, ell_table with the tabulated and
+ * interpolated kernel (App. F). Either output may be NULL. */
+lmg_status lmg_map_error(const lmg_table* t, int n, const double* x, double* ell_exact, double* ell_table);
+
+void lmg_table_destroy(lmg_table* t);
+
+/* ------------------------------------------------------------------- plans
+ * A plan holds, in a caller-owned device workspace, everything the kernels
+ * derive from the uv coordinates alone: the first tap cell and fractional
+ * offsets of every visibility (computed in FP64) and a counting sort of the
+ * visibilities by uv tile with per-tile work lists. Build one per uv set and
+ * reuse it for every grid / degrid / image / prediction call on that set
+ * (the paper notes that this per-visibility work need be done only once,
+ * Sec. 6.2). The plan keeps pointers into `workspace` and a reference to
+ * `table`: both must outlive it.
+ *
+ * N: power of two in [max(64, 2W), 16384]; x0 * N * 2 an integer (taken
+ * from the table). nvis >= 0. uv: device (nvis, 2) float64.
+ * lmg_plan_create synchronizes `stream` once, to size the work lists; it
+ * leaves LMG_EDATA to be reported by lmg_plan_check when a coordinate is NaN
+ * or infinite (such visibilities are dropped from every later call).
+ */
+typedef struct lmg_plan lmg_plan;
+
+lmg_status lmg_plan_workspace_size(int N, int W, int64_t nvis, lmg_precision prec, size_t* bytes);
+lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, int64_t nvis,
+                           const double* uv, void* workspace, size_t ws_bytes, void* stream,
+                           lmg_plan** out);
+/* LMG_OK, or LMG_EDATA if non-finite coordinates were dropped. Host query. */
+lmg_status lmg_plan_check(const lmg_plan* p);
+/* Tile edge, number of work items and occupied tiles (any pointer may be NULL). */
+lmg_status lmg_plan_info(const lmg_plan* p, int* tile, int* n_items, int* n_busy_tiles, int64_t* n_valid);
+void lmg_plan_destroy(lmg_plan* p);
+
+/* Scratch a planned call needs beyond its inputs and outputs (device bytes). */
+lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes);
+#define LMG_OP_GRID 0
+#define LMG_OP_DEGRID 1
+#define LMG_OP_DIRTY 2
+#define LMG_OP_PREDICT 3
+
+/* --------------------------------------------------------- planned calls */
+
+/* Gridding (Eq. 5 in 2D): grid[m][n] = sum_k w_k V_k C(m - v_k) C(n - u_k),
+ * OVERWRITING the N x N device grid. vis: device complex (nvis), w: device
+ * float32 (nvis) or NULL for unit weights. */
+lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid,
+                            void* scratch, size_t scratch_bytes, void* stream);
+
+/* Degridding, the transpose of gridding (Sec. 1, Sec. 5):
+ * vis_out[k] = sum_{m,n} C(m - v_k) C(n - u_k) grid[m][n]. Weights do not
+ * apply. vis_out: device complex (nvis), overwritten. */
+lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out,
+                              void* scratch, size_t scratch_bytes, void* stream);
+
+/* Dirty image (Eq. 4 in 2D): grid, inverse 2D FFT (exponent +i2pi), multiply
+ * by h(x_p) h(y_q) and keep |x|, |y| <= x0. image: device complex
+ * (2 x0 N)^2, overwritten. No normalisation by sum(w). */
+lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image,
+                                        void* scratch, size_t scratch_bytes, void* stream);
+
+/* Prediction (Eq. 2 through the FFT, Sec. 5): multiply the image by
+ * h(x_p) h(y_q), zero-pad to N x N, forward 2D FFT (exponent -i2pi) and
+ * degrid. image: device complex (2 x0 N)^2; vis_out: device complex (nvis). */
+lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image, void* vis_out,
+                                            void* scratch, size_t scratch_bytes, void* stream);
+
+/* ------------------------------------------------ one-shot (unplanned) calls
+ * Build a plan inside `workspace`, run the call, and release the plan. The
+ * workspace size comes from lmg_workspace_size for the same (N, W, nvis,
+ * prec, op). These synchronize `stream` once (plan sizing). */
+lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes);
+lmg_status lmg_grid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                    const void* vis, const float* w, void* grid, void* workspace, size_t ws_bytes, void* stream);
+lmg_status lmg_degrid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                      const void* grid, void* vis_out, void* workspace, size_t ws_bytes, void* stream);
+lmg_status lmg_make_dirty_image(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                                const void* vis, const float* w, void* image, void* workspace, size_t ws_bytes,
+                                void* stream);
+lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                                    const void* image, void* vis_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------- 2D FFT building block
+ * Centred 2D transform F[q][p] = sum_{m,n} G[m][n] exp(sign i 2 pi (n p + m q) / N)
+ * of an N x N device array in place of `data` (all indices centred in
+ * [-N/2, N/2)); sign = +1 or -1. scratch: N*N complex device elements. */
+lmg_status lmg_fft2_centred(int N, lmg_precision prec, int sign, void* data, void* scratch, void* stream);
+
+/* ------------------------------------------------------------------ tracing
+ * When enabled, every kernel the library launches is bracketed by a pair of
+ * HIP events recorded on the launch stream. lmg_trace_report synchronizes
+ * those events and writes one line per kernel name, "name count total_ms",
+ * into `buf` (NUL-terminated, truncated to `len`), then clears the record.
+ * Also enabled by the environment variable LMG_TRACE=1. Not thread-safe
+ * with respect to concurrent launches from several host threads. */
+lmg_status lmg_trace_enable(int on);
+lmg_status lmg_trace_report(char* buf, size_t len);
+
+const char* lmg_status_string(lmg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMGRID_H */

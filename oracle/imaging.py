@@ -58,6 +58,30 @@ def grid(uv: np.ndarray, vis: np.ndarray, weights, N: int, table: Table) -> np.n
     return G.reshape(N, N)
 
 
+def grid_cells(uv: np.ndarray, vis: np.ndarray, weights, N: int, table: Table, cells) -> np.ndarray:
+    """Selected grid values G[row, col] (storage indices) by the definition of Eq. (5), summing only the
+    visibilities whose W x W footprint contains the cell. For checking large grids at sample points."""
+    uv = np.asarray(uv, dtype=np.float64)
+    vis = np.asarray(vis, dtype=np.complex128)
+    w = np.ones(len(uv)) if weights is None else np.asarray(weights, dtype=np.float64)
+    W = table.W
+    nu, _ = tap_geometry(uv[:, 0], W)
+    nv, _ = tap_geometry(uv[:, 1], W)
+    cu0 = (nu + N // 2) % N
+    cv0 = (nv + N // 2) % N
+    out = np.zeros(len(cells), dtype=np.complex128)
+    for i, (r, c) in enumerate(cells):
+        jv = (r - cv0) % N
+        ju = (c - cu0) % N
+        sel = np.nonzero((jv < W) & (ju < W))[0]
+        if len(sel) == 0:
+            continue
+        wu = table.weights(tap_geometry(uv[sel, 0], W)[1])[np.arange(len(sel)), ju[sel]]
+        wv = table.weights(tap_geometry(uv[sel, 1], W)[1])[np.arange(len(sel)), jv[sel]]
+        out[i] = np.sum(w[sel] * vis[sel] * wv * wu)
+    return out
+
+
 def degrid(uv: np.ndarray, G: np.ndarray, table: Table) -> np.ndarray:
     """V_k = sum_{m,n} C(m - v_k) C(n - u_k) G_{m,n}: the transpose of :func:`grid` (Sec. 1, Sec. 5)."""
     uv = np.asarray(uv, dtype=np.float64)

@@ -1,0 +1,430 @@
+"""Least-misfit gridding and degridding on AMD MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``liblmgrid.so`` (declared in
+``include/lmgrid.h``). Every step of the path runs in the library's HIP
+kernels; this module only marshals torch tensors (device memory and the
+current stream) into pointers. If the library is not built, importing works
+but every call raises :class:`LibraryMissing` -- there is no fallback.
+
+Method: Ye, Gull, Tan & Nikolic, "Optimal gridding and degridding in radio
+interferometry imaging", MNRAS 2019.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+__all__ = [
+    "F32", "F32_KAHAN", "F64", "LmgError", "LibraryMissing", "Table", "Plan", "library_path", "load",
+    "grid", "degrid", "make_dirty_image", "predict_visibilities", "fft2_centred", "trace_enable", "trace_report",
+]
+
+F32, F32_KAHAN, F64 = 0, 1, 2
+OP_GRID, OP_DEGRID, OP_DIRTY, OP_PREDICT = 0, 1, 2, 3
+NG = 32
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class LmgError(RuntimeError):
+    """A non-zero lmg_status."""
+
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_status_string(status)} ({status})")
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "liblmgrid.so")
+
+
+def _status_string(s: int) -> str:
+    lib = load()
+    return lib.lmg_status_string(s).decode()
+
+
+def load():
+    """Load the in-tree HIP library (raises LibraryMissing if it was not built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise LibraryMissing(f"{path} not found: build it with `python -m paper_1906_07102_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I, D, Z, I64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_int64
+    PD = ctypes.POINTER(ctypes.c_double)
+    PI = ctypes.POINTER(ctypes.c_int)
+    PZ = ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "lmg_table_create": (I, [I, D, I, I, ctypes.POINTER(P)]),
+        "lmg_table_create_from_h": (I, [I, D, I, I, PD, ctypes.POINTER(P)]),
+        "lmg_table_create_from_nodes": (I, [I, D, I, I, PD, PD, ctypes.POINTER(P)]),
+        "lmg_table_info": (I, [P, PI, PD, PI, PI, PD]),
+        "lmg_table_export": (I, [P, PD, PD]),
+        "lmg_table_kernel": (I, [P, I, PD, PD]),
+        "lmg_correction": (I, [P, I, PD]),
+        "lmg_map_error": (I, [P, I, PD, PD, PD]),
+        "lmg_table_destroy": (None, [P]),
+        "lmg_plan_workspace_size": (I, [I, I, I64, I, PZ]),
+        "lmg_plan_create": (I, [P, I, I, I64, P, P, Z, P, ctypes.POINTER(P)]),
+        "lmg_plan_check": (I, [P]),
+        "lmg_plan_info": (I, [P, PI, PI, PI, ctypes.POINTER(I64)]),
+        "lmg_plan_destroy": (None, [P]),
+        "lmg_plan_scratch_size": (I, [P, I, PZ]),
+        "lmg_grid_planned": (I, [P, P, P, P, P, Z, P]),
+        "lmg_degrid_planned": (I, [P, P, P, P, Z, P]),
+        "lmg_make_dirty_image_planned": (I, [P, P, P, P, P, Z, P]),
+        "lmg_predict_visibilities_planned": (I, [P, P, P, P, Z, P]),
+        "lmg_workspace_size": (I, [I, I, D, I64, I, I, PZ]),
+        "lmg_grid": (I, [P, I, I, I64, P, P, P, P, P, Z, P]),
+        "lmg_degrid": (I, [P, I, I, I64, P, P, P, P, Z, P]),
+        "lmg_make_dirty_image": (I, [P, I, I, I64, P, P, P, P, P, Z, P]),
+        "lmg_predict_visibilities": (I, [P, I, I, I64, P, P, P, P, Z, P]),
+        "lmg_fft2_centred": (I, [I, I, I, P, P, P]),
+        "lmg_trace_enable": (I, [I]),
+        "lmg_trace_report": (I, [ctypes.c_char_p, Z]),
+        "lmg_status_string": (ctypes.c_char_p, [I]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def exported_symbols():
+    """Names the C ABI exports (for the build check)."""
+    load()
+    return [n for n in dir(_LIB) if n.startswith("lmg_")]
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise LmgError(status, what)
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+# --------------------------------------------------------------------- tables
+class Table:
+    """A least-misfit gridding table (host object): h on 33 points, tabulated C, interpolation degree."""
+
+    def __init__(self, handle):
+        self._h = ctypes.c_void_p(handle) if not isinstance(handle, ctypes.c_void_p) else handle
+        self._lib = load()
+        W, x0, Ms, deg, E = ctypes.c_int(), ctypes.c_double(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(self._lib.lmg_table_info(self._h, ctypes.byref(W), ctypes.byref(x0), ctypes.byref(Ms),
+                                        ctypes.byref(deg), ctypes.byref(E)), "lmg_table_info")
+        self.W, self.x0, self.Ms, self.degree, self.integrated_misfit = W.value, x0.value, Ms.value, deg.value, E.value
+        self.table_size = self.W * self.Ms
+
+    @classmethod
+    def create(cls, W: int, x0: float, table_size: int, degree: int = 3) -> "Table":
+        out = ctypes.c_void_p()
+        _check(load().lmg_table_create(W, x0, table_size, degree, ctypes.byref(out)), "lmg_table_create")
+        return cls(out)
+
+    @classmethod
+    def from_h(cls, W: int, x0: float, table_size: int, degree: int, h) -> "Table":
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        if h.shape != (NG + 1,):
+            raise ValueError("h must have 33 samples")
+        out = ctypes.c_void_p()
+        _check(load().lmg_table_create_from_h(W, x0, table_size, degree, _dptr(h), ctypes.byref(out)),
+               "lmg_table_create_from_h")
+        return cls(out)
+
+    @classmethod
+    def from_nodes(cls, W: int, x0: float, table_size: int, degree: int, h, nodes) -> "Table":
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        Ms = table_size // W
+        if h.shape != (NG + 1,) or nodes.shape != (W, Ms + 1 + degree):
+            raise ValueError("bad h or nodes shape")
+        out = ctypes.c_void_p()
+        _check(load().lmg_table_create_from_nodes(W, x0, table_size, degree, _dptr(h), _dptr(nodes),
+                                                  ctypes.byref(out)), "lmg_table_create_from_nodes")
+        return cls(out)
+
+    def export(self):
+        h = np.zeros(NG + 1)
+        nodes = np.zeros((self.W, self.Ms + 1 + self.degree))
+        _check(self._lib.lmg_table_export(self._h, _dptr(h), _dptr(nodes)), "lmg_table_export")
+        return h, nodes
+
+    def kernel(self, delta) -> np.ndarray:
+        d = np.ascontiguousarray(np.atleast_1d(delta), dtype=np.float64)
+        out = np.zeros((len(d), self.W))
+        _check(self._lib.lmg_table_kernel(self._h, len(d), _dptr(d), _dptr(out)), "lmg_table_kernel")
+        return out
+
+    def correction(self, N: int) -> np.ndarray:
+        out = np.zeros(N)
+        _check(self._lib.lmg_correction(self._h, N, _dptr(out)), "lmg_correction")
+        return out
+
+    def map_error(self, x):
+        x = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+        a = np.zeros(len(x))
+        b = np.zeros(len(x))
+        _check(self._lib.lmg_map_error(self._h, len(x), _dptr(x), _dptr(a), _dptr(b)), "lmg_map_error")
+        return a, b
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        try:
+            if self._h:
+                self._lib.lmg_table_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec_of(dtype, kahan: bool) -> int:
+    torch = _torch()
+    if dtype == torch.complex128:
+        return F64
+    if dtype == torch.complex64:
+        return F32_KAHAN if kahan else F32
+    raise TypeError(f"visibilities must be complex64 or complex128, got {dtype}")
+
+
+def _cdtype(prec: int):
+    torch = _torch()
+    return torch.complex128 if prec == F64 else torch.complex64
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_tensor(t, name, dtype=None, shape=None, device=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _bytes(n: int, device):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+class Plan:
+    """Per-uv-set state (tap cells, offsets, tile sort, work lists) in a torch-owned workspace."""
+
+    def __init__(self, table: Table, N: int, uv, precision: int = F32, stream=None):
+        torch = _torch()
+        _check_tensor(uv, "uv", torch.float64)
+        if uv.dim() != 2 or uv.shape[1] != 2:
+            raise ValueError("uv must be (nvis, 2)")
+        self.lib = load()
+        self.table, self.N, self.precision = table, int(N), int(precision)
+        self.nvis = int(uv.shape[0])
+        self.device = uv.device
+        self.M = int(round(2 * table.x0 * N))
+        nb = ctypes.c_size_t()
+        _check(self.lib.lmg_plan_workspace_size(self.N, table.W, self.nvis, self.precision, ctypes.byref(nb)),
+               "lmg_plan_workspace_size")
+        self.workspace = _bytes(nb.value, uv.device)
+        self.uv = uv
+        h = ctypes.c_void_p()
+        with torch.cuda.device(uv.device):
+            _check(self.lib.lmg_plan_create(table.handle, self.N, self.precision, self.nvis, _ptr(uv),
+                                            _ptr(self.workspace), nb.value, _stream_handle(stream), ctypes.byref(h)),
+                   "lmg_plan_create")
+        self._h = h
+        self._scratch = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        t, ni, nb, nv = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int64()
+        _check(self.lib.lmg_plan_info(self._h, ctypes.byref(t), ctypes.byref(ni), ctypes.byref(nb), ctypes.byref(nv)),
+               "lmg_plan_info")
+        return {"tile": t.value, "items": ni.value, "busy_tiles": nb.value, "valid": nv.value}
+
+    def check(self) -> int:
+        return self.lib.lmg_plan_check(self._h)
+
+    def scratch(self, op: int):
+        if op not in self._scratch:
+            n = ctypes.c_size_t()
+            _check(self.lib.lmg_plan_scratch_size(self._h, op, ctypes.byref(n)), "lmg_plan_scratch_size")
+            self._scratch[op] = _bytes(n.value, self.device)
+        return self._scratch[op]
+
+    def _vis_dtype(self):
+        return _cdtype(self.precision)
+
+    def grid(self, vis, weights=None, out=None, stream=None):
+        torch = _torch()
+        _check_tensor(vis, "vis", self._vis_dtype(), (self.nvis,), self.device)
+        if weights is not None:
+            _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "grid", self._vis_dtype(), (self.N, self.N), self.device)
+        sc = self.scratch(OP_GRID)
+        _check(self.lib.lmg_grid_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), _ptr(sc), sc.numel(),
+                                         _stream_handle(stream)), "lmg_grid_planned")
+        return out
+
+    def degrid(self, grid, out=None, stream=None):
+        torch = _torch()
+        _check_tensor(grid, "grid", self._vis_dtype(), (self.N, self.N), self.device)
+        if out is None:
+            out = torch.empty(self.nvis, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "vis_out", self._vis_dtype(), (self.nvis,), self.device)
+        _check(self.lib.lmg_degrid_planned(self._h, _ptr(grid), _ptr(out), ctypes.c_void_p(0), 0,
+                                           _stream_handle(stream)), "lmg_degrid_planned")
+        return out
+
+    def make_dirty_image(self, vis, weights=None, out=None, stream=None):
+        torch = _torch()
+        _check_tensor(vis, "vis", self._vis_dtype(), (self.nvis,), self.device)
+        if weights is not None:
+            _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
+        if out is None:
+            out = torch.empty((self.M, self.M), dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "image", self._vis_dtype(), (self.M, self.M), self.device)
+        sc = self.scratch(OP_DIRTY)
+        _check(self.lib.lmg_make_dirty_image_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), _ptr(sc),
+                                                     sc.numel(), _stream_handle(stream)),
+               "lmg_make_dirty_image_planned")
+        return out
+
+    def predict_visibilities(self, image, out=None, stream=None):
+        torch = _torch()
+        _check_tensor(image, "image", self._vis_dtype(), (self.M, self.M), self.device)
+        if out is None:
+            out = torch.empty(self.nvis, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "vis_out", self._vis_dtype(), (self.nvis,), self.device)
+        sc = self.scratch(OP_PREDICT)
+        _check(self.lib.lmg_predict_visibilities_planned(self._h, _ptr(image), _ptr(out), _ptr(sc), sc.numel(),
+                                                         _stream_handle(stream)),
+               "lmg_predict_visibilities_planned")
+        return out
+
+    def __del__(self):
+        try:
+            if self._h:
+                self.lib.lmg_plan_destroy(self._h)
+                self._h = None
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ one-shot calls
+def _oneshot_ws(table, N, nvis, prec, op, device):
+    n = ctypes.c_size_t()
+    _check(load().lmg_workspace_size(N, table.W, table.x0, nvis, prec, op, ctypes.byref(n)), "lmg_workspace_size")
+    return _bytes(n.value, device), n.value
+
+
+def grid(table: Table, N: int, uv, vis, weights=None, kahan: bool = False, stream=None):
+    """One-shot gridding (builds a plan internally); returns the N x N grid."""
+    torch = _torch()
+    prec = _prec_of(vis.dtype, kahan)
+    _check_tensor(uv, "uv", torch.float64)
+    out = torch.empty((N, N), dtype=vis.dtype, device=vis.device)
+    ws, nb = _oneshot_ws(table, N, vis.numel(), prec, OP_GRID, vis.device)
+    _check(load().lmg_grid(table.handle, N, prec, vis.numel(), _ptr(uv), _ptr(vis), _ptr(weights), _ptr(out),
+                           _ptr(ws), nb, _stream_handle(stream)), "lmg_grid")
+    return out
+
+
+def degrid(table: Table, N: int, uv, grid_, stream=None):
+    torch = _torch()
+    prec = _prec_of(grid_.dtype, False)
+    nvis = uv.shape[0]
+    out = torch.empty(nvis, dtype=grid_.dtype, device=grid_.device)
+    ws, nb = _oneshot_ws(table, N, nvis, prec, OP_DEGRID, grid_.device)
+    _check(load().lmg_degrid(table.handle, N, prec, nvis, _ptr(uv), _ptr(grid_), _ptr(out), _ptr(ws), nb,
+                             _stream_handle(stream)), "lmg_degrid")
+    return out
+
+
+def make_dirty_image(table: Table, N: int, uv, vis, weights=None, kahan: bool = False, stream=None):
+    torch = _torch()
+    prec = _prec_of(vis.dtype, kahan)
+    M = int(round(2 * table.x0 * N))
+    out = torch.empty((M, M), dtype=vis.dtype, device=vis.device)
+    ws, nb = _oneshot_ws(table, N, vis.numel(), prec, OP_DIRTY, vis.device)
+    _check(load().lmg_make_dirty_image(table.handle, N, prec, vis.numel(), _ptr(uv), _ptr(vis), _ptr(weights),
+                                       _ptr(out), _ptr(ws), nb, _stream_handle(stream)), "lmg_make_dirty_image")
+    return out
+
+
+def predict_visibilities(table: Table, N: int, uv, image, stream=None):
+    torch = _torch()
+    prec = _prec_of(image.dtype, False)
+    nvis = uv.shape[0]
+    out = torch.empty(nvis, dtype=image.dtype, device=image.device)
+    ws, nb = _oneshot_ws(table, N, nvis, prec, OP_PREDICT, image.device)
+    _check(load().lmg_predict_visibilities(table.handle, N, prec, nvis, _ptr(uv), _ptr(image), _ptr(out), _ptr(ws),
+                                           nb, _stream_handle(stream)), "lmg_predict_visibilities")
+    return out
+
+
+def trace_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events (per-kernel timing)."""
+    _check(load().lmg_trace_enable(1 if on else 0), "lmg_trace_enable")
+
+
+def trace_report() -> dict:
+    """{kernel name: (launches, total ms)} since the last report; synchronizes the recorded events."""
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load().lmg_trace_report(buf, len(buf)), "lmg_trace_report")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, n, ms = line.split()
+        out[name] = (int(n), float(ms))
+    return out
+
+
+def fft2_centred(data, sign: int, stream=None):
+    """In-place centred 2D FFT of an N x N complex tensor (exponent sign * i 2 pi)."""
+    N = data.shape[0]
+    prec = _prec_of(data.dtype, False)
+    cs = 16 if prec == F64 else 8
+    scratch = _bytes(((N * N * cs + 255) // 256) * 256 + N * cs, data.device)
+    _check(load().lmg_fft2_centred(N, prec, sign, _ptr(data), _ptr(scratch), _stream_handle(stream)),
+           "lmg_fft2_centred")
+    return data

@@ -1,0 +1,502 @@
+// C ABI: plans, gridding, degridding, dirty images and prediction.
+//
+// Host-side argument checking, workspace layout and kernel sequencing. Every
+// device buffer is caller-owned; the library never allocates device memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "lmg_internal.h"
+#include "trace.h"
+
+using namespace lmg;
+
+struct lmg_plan {
+    const lmg_table* table = nullptr;
+    lmg_precision prec = LMG_F32;
+    PlanGeom g{};
+    int64_t nvis = 0;
+    int64_t n_valid = 0;
+    int n_items = 0;
+    int n_busy = 0;
+    int max_items = 0;
+    int cap = 0;
+    int M = 0;                  // retained image size 2 x0 N
+    bool bad_data = false;
+    int* flags = nullptr;
+    int* tile_count = nullptr;
+    int* tile_start = nullptr;
+    int* item_start = nullptr;
+    int* cursor = nullptr;
+    int4* items = nullptr;
+    int* perm = nullptr;
+    uint16_t* loc = nullptr;
+    void* dlt = nullptr;
+    void* coef = nullptr;
+    void* twiddle = nullptr;
+    void* hpix = nullptr;
+};
+
+namespace {
+
+#define LMG_HIP(call)                                  \
+    do {                                               \
+        if ((call) != hipSuccess) return LMG_EHIP;     \
+    } while (0)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int env_int(const char* name, int fallback) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return fallback;
+    const int x = std::atoi(v);
+    return x > 0 ? x : fallback;
+}
+
+int choose_tile(int N, lmg_precision prec) {
+    int T = env_int("LMG_TILE", prec == LMG_F32 ? 64 : 32);
+    if (!is_pow2(T) || T < 8) T = 32;
+    T = std::min(T, 128);
+    while (T > N) T /= 2;
+    while (N / T > 128) T *= 2;    // keeps the plan's LDS histogram at <= 16384 tiles
+    return T;
+}
+
+int choose_cap() { return env_int("LMG_CAP", 8192); }
+
+size_t real_size(lmg_precision p) { return p == LMG_F64 ? 8 : 4; }
+size_t cplx_size(lmg_precision p) { return 2 * real_size(p); }
+size_t patch_cell_size(lmg_precision p) { return p == LMG_F32 ? 8 : 16; }
+
+struct Layout {
+    size_t flags, tile_count, tile_start, item_start, cursor, items, perm, loc, dlt, coef, twiddle, hpix, total;
+    int max_items;
+};
+
+Layout plan_layout(int N, int T, int64_t nvis, lmg_precision prec, int cap) {
+    Layout L{};
+    const int64_t ntiles = static_cast<int64_t>(N / T) * (N / T);
+    L.max_items = static_cast<int>(std::min<int64_t>(ntiles, nvis) + (nvis + cap - 1) / cap + 1);
+    size_t o = 0;
+    auto take = [&o](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
+    L.flags = take(16 * sizeof(int));
+    L.tile_count = take(ntiles * sizeof(int));
+    L.tile_start = take((ntiles + 1) * sizeof(int));
+    L.item_start = take((ntiles + 1) * sizeof(int));
+    L.cursor = take(ntiles * sizeof(int));
+    L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
+    L.perm = take(static_cast<size_t>(nvis) * sizeof(int));
+    L.loc = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
+    L.dlt = take(static_cast<size_t>(nvis) * cplx_size(prec));
+    L.coef = take(kMaxLdsTableBytes * 2);
+    L.twiddle = take(static_cast<size_t>(N) * cplx_size(prec));
+    L.hpix = take(static_cast<size_t>(N) * real_size(prec));
+    L.total = o;
+    return L;
+}
+
+size_t scratch_for(int N, int W, int T, int M, int items, lmg_precision prec, int op) {
+    const size_t P = static_cast<size_t>(T + W - 1);
+    const size_t patches = align_up(static_cast<size_t>(items) * P * P * patch_cell_size(prec));
+    const size_t grid = align_up(static_cast<size_t>(N) * N * cplx_size(prec));
+    const size_t tmp = align_up(static_cast<size_t>(M) * N * cplx_size(prec));
+    switch (op) {
+        case LMG_OP_GRID: return patches;
+        case LMG_OP_DEGRID: return 0;
+        case LMG_OP_DIRTY: return grid + tmp + patches;
+        case LMG_OP_PREDICT: return grid + tmp;
+    }
+    return 0;
+}
+
+bool valid_grid(int N, int W, double x0, int* M) {
+    if (!is_pow2(N) || N < 64 || N > 8192 || N < 2 * W) return false;
+    const double m = 2.0 * x0 * N;
+    if (std::fabs(m - std::round(m)) > 1e-9) return false;
+    *M = static_cast<int>(std::lround(m));
+    return *M >= 2 && *M <= N && (*M % 2) == 0;
+}
+
+// Host caches (never freed) of FFT twiddles and correction vectors.
+std::mutex g_cache_mu;
+std::map<int, std::vector<double>>& twiddle_cache() {
+    static std::map<int, std::vector<double>> c;
+    return c;
+}
+const std::vector<double>& twiddles_f64(int N) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto& c = twiddle_cache();
+    auto it = c.find(N);
+    if (it != c.end()) return it->second;
+    std::vector<double> tw(2 * static_cast<size_t>(N));
+    for (int t = 0; t < N; ++t) {
+        const double a = 2.0 * 3.14159265358979323846 * (static_cast<double>(t) / N);
+        tw[2 * t] = std::cos(a);
+        tw[2 * t + 1] = -std::sin(a);
+    }
+    return c.emplace(N, std::move(tw)).first->second;
+}
+std::map<int, std::vector<float>>& twiddle32_cache() {
+    static std::map<int, std::vector<float>> c;
+    return c;
+}
+const std::vector<float>& twiddles_f32(int N) {
+    const std::vector<double>& d = twiddles_f64(N);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto& c = twiddle32_cache();
+    auto it = c.find(N);
+    if (it != c.end()) return it->second;
+    std::vector<float> f(d.begin(), d.end());
+    return c.emplace(N, std::move(f)).first->second;
+}
+
+std::once_flag g_attr_once;
+hipError_t g_attr_err = hipSuccess;
+hipError_t ensure_attributes() {
+    std::call_once(g_attr_once, [] { g_attr_err = set_kernel_attributes(); });
+    return g_attr_err;
+}
+
+lmg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return LMG_OK;
+    LMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    return LMG_OK;
+}
+
+lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* patches, hipStream_t s) {
+    const lmg_table* t = p->table;
+    GridArgs a{};
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
+    a.n_items = p->n_items; a.dlo = delta_low(t->W);
+    a.items = p->items; a.perm = p->perm; a.loc = p->loc; a.dlt = p->dlt; a.coef = p->coef;
+    a.vis = vis; a.w = w; a.patches = patches;
+    {
+        TraceScope ts("grid_items", s);
+        LMG_HIP(launch_grid(p->prec, a, s));
+    }
+    AssembleArgs b{};
+    b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx;
+    b.item_start = p->item_start; b.patches = patches; b.grid = grid;
+    TraceScope ts("assemble", s);
+    LMG_HIP(launch_assemble(p->prec, b, s));
+    return LMG_OK;
+}
+
+lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, hipStream_t s) {
+    const lmg_table* t = p->table;
+    if (p->bad_data && p->nvis > 0) LMG_HIP(hipMemsetAsync(vis_out, 0, static_cast<size_t>(p->nvis) * cplx_size(p->prec), s));
+    DegridArgs a{};
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
+    a.n_items = p->n_items; a.dlo = delta_low(t->W);
+    a.items = p->items; a.perm = p->perm; a.loc = p->loc; a.dlt = p->dlt; a.coef = p->coef;
+    a.grid = grid; a.vis_out = vis_out;
+    TraceScope ts("degrid_items", s);
+    LMG_HIP(launch_degrid(p->prec, a, s));
+    return LMG_OK;
+}
+
+FftArgs fft_args(int N, int sign, const void* tw) {
+    FftArgs f{};
+    f.N = N;
+    f.sign = sign;
+    f.twiddle = tw;
+    return f;
+}
+
+bool scratch_ok(const lmg_plan* p, int op, void* scratch, size_t bytes) {
+    const size_t need = scratch_for(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->prec, op);
+    return need == 0 || (scratch && bytes >= need);
+}
+
+}  // namespace
+
+extern "C" {
+
+lmg_status lmg_plan_workspace_size(int N, int W, int64_t nvis, lmg_precision prec, size_t* bytes) {
+    if (!bytes || !is_pow2(N) || N < 64 || N > 8192 || W < 1 || W > kMaxW || nvis < 0 || nvis > INT32_MAX ||
+        prec < LMG_F32 || prec > LMG_F64)
+        return LMG_EINVAL;
+    *bytes = plan_layout(N, choose_tile(N, prec), nvis, prec, choose_cap()).total;
+    return LMG_OK;
+}
+
+lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                           void* workspace, size_t ws_bytes, void* stream, lmg_plan** out) {
+    int M = 0;
+    if (!table || !out || prec < LMG_F32 || prec > LMG_F64 || nvis < 0 || nvis > INT32_MAX ||
+        !valid_grid(N, table->W, table->x0, &M) || (nvis > 0 && !uv))
+        return LMG_EINVAL;
+    const size_t tab_bytes = (prec == LMG_F64 ? table->coef64.size() * 8 : table->coef32.size() * 4);
+    if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
+    const int T = choose_tile(N, prec);
+    const int cap = choose_cap();
+    const Layout L = plan_layout(N, T, nvis, prec, cap);
+    if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
+    if (ensure_attributes() != hipSuccess) return LMG_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::unique_ptr<lmg_plan> p(new (std::nothrow) lmg_plan);
+    if (!p) return LMG_EINVAL;
+    char* base = static_cast<char*>(workspace);
+    p->table = table;
+    p->prec = prec;
+    p->g.N = N; p->g.W = table->W; p->g.T = T; p->g.ntx = N / T; p->g.ntiles = (N / T) * (N / T);
+    p->g.ref = tap_reference(table->W);
+    p->nvis = nvis;
+    p->cap = cap;
+    p->max_items = L.max_items;
+    p->M = M;
+    p->flags = reinterpret_cast<int*>(base + L.flags);
+    p->tile_count = reinterpret_cast<int*>(base + L.tile_count);
+    p->tile_start = reinterpret_cast<int*>(base + L.tile_start);
+    p->item_start = reinterpret_cast<int*>(base + L.item_start);
+    p->cursor = reinterpret_cast<int*>(base + L.cursor);
+    p->items = reinterpret_cast<int4*>(base + L.items);
+    p->perm = reinterpret_cast<int*>(base + L.perm);
+    p->loc = reinterpret_cast<uint16_t*>(base + L.loc);
+    p->dlt = base + L.dlt;
+    p->coef = base + L.coef;
+    p->twiddle = base + L.twiddle;
+    p->hpix = base + L.hpix;
+
+    // Constant tables: kernel coefficients, FFT twiddles, correction h(x_p).
+    std::vector<double> h(N);
+    if (lmg_correction(table, N, h.data()) != LMG_OK) return LMG_EINVAL;
+    if (prec == LMG_F64) {
+        if (upload(p->coef, table->coef64.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->twiddle, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->hpix, h.data(), sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
+    } else {
+        std::vector<float> hf(h.begin(), h.end());
+        if (upload(p->coef, table->coef32.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->twiddle, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->hpix, hf.data(), sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
+        LMG_HIP(hipStreamSynchronize(s));       // hf goes out of scope
+    }
+    LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
+    LMG_HIP(hipMemsetAsync(p->tile_count, 0, sizeof(int) * p->g.ntiles, s));
+    {
+        TraceScope ts("plan_count", s);
+        LMG_HIP(launch_plan_count(uv, nvis, p->g, p->tile_count, p->flags, s));
+    }
+    {
+        TraceScope ts("plan_scan", s);
+        LMG_HIP(launch_plan_scan(p->g, p->tile_count, p->tile_start, p->item_start, p->cursor, p->items, p->flags,
+                                 cap, s));
+    }
+    {
+        TraceScope ts("plan_scatter", s);
+        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->cursor, p->perm, p->loc,
+                                    p->dlt, s));
+    }
+    int flags[4] = {0, 0, 0, 0};
+    LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LMG_HIP(hipStreamSynchronize(s));
+    p->bad_data = flags[0] != 0;
+    p->n_items = flags[1];
+    p->n_valid = flags[2];
+    p->n_busy = flags[3];
+    if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
+    *out = p.release();
+    return LMG_OK;
+}
+
+lmg_status lmg_plan_check(const lmg_plan* p) {
+    if (!p) return LMG_EINVAL;
+    return p->bad_data ? LMG_EDATA : LMG_OK;
+}
+
+lmg_status lmg_plan_info(const lmg_plan* p, int* tile, int* n_items, int* n_busy, int64_t* n_valid) {
+    if (!p) return LMG_EINVAL;
+    if (tile) *tile = p->g.T;
+    if (n_items) *n_items = p->n_items;
+    if (n_busy) *n_busy = p->n_busy;
+    if (n_valid) *n_valid = p->n_valid;
+    return LMG_OK;
+}
+
+void lmg_plan_destroy(lmg_plan* p) { delete p; }
+
+lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes) {
+    if (!p || !bytes || op < LMG_OP_GRID || op > LMG_OP_PREDICT) return LMG_EINVAL;
+    *bytes = scratch_for(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->prec, op);
+    return LMG_OK;
+}
+
+lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, void* scratch,
+                            size_t scratch_bytes, void* stream) {
+    if (!p || !grid || (p->nvis > 0 && !vis)) return LMG_EINVAL;
+    if (!scratch_ok(p, LMG_OP_GRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    return run_grid(p, vis, w, grid, scratch, static_cast<hipStream_t>(stream));
+}
+
+lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out, void* scratch, size_t scratch_bytes,
+                              void* stream) {
+    (void)scratch;
+    (void)scratch_bytes;
+    if (!p || !grid || (p->nvis > 0 && !vis_out)) return LMG_EINVAL;
+    return run_degrid(p, grid, vis_out, static_cast<hipStream_t>(stream));
+}
+
+lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image, void* scratch,
+                                        size_t scratch_bytes, void* stream) {
+    if (!p || !image || (p->nvis > 0 && !vis)) return LMG_EINVAL;
+    if (!scratch_ok(p, LMG_OP_DIRTY, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int N = p->g.N, M = p->M;
+    const size_t cs = cplx_size(p->prec);
+    char* sc = static_cast<char*>(scratch);
+    void* grid = sc;
+    void* tmp = sc + align_up(static_cast<size_t>(N) * N * cs);
+    void* patches = static_cast<char*>(tmp) + align_up(static_cast<size_t>(M) * N * cs);
+    lmg_status st = run_grid(p, vis, w, grid, patches, s);
+    if (st != LMG_OK) return st;
+    const bool f64 = p->prec == LMG_F64;
+    // Rows m of the grid: transform over n, keep the central M outputs, write transposed (tmp is M x N).
+    FftArgs a = fft_args(N, +1, p->twiddle);
+    a.nrows = N; a.src = grid; a.src_pitch = N; a.in_count = N; a.in_pos = 0;
+    a.dst = tmp; a.dst_pitch = N; a.out_count = M; a.out_pos = N / 2 - M / 2;
+    {
+        TraceScope ts("fft_rows_inverse", s);
+        LMG_HIP(launch_fft_pass(f64, a, s));
+    }
+    // Rows p of tmp: transform over m, keep the central M outputs, apply h(x_p) h(y_q), write image[q][p].
+    FftArgs b = fft_args(N, +1, p->twiddle);
+    b.nrows = M; b.src = tmp; b.src_pitch = N; b.in_count = N; b.in_pos = 0;
+    b.dst = image; b.dst_pitch = M; b.out_count = M; b.out_pos = N / 2 - M / 2;
+    b.h_out = p->hpix; b.h_row = p->hpix; b.row_off = N / 2 - M / 2;
+    TraceScope ts("fft_cols_inverse_correct_crop", s);
+    LMG_HIP(launch_fft_pass(f64, b, s));
+    return LMG_OK;
+}
+
+lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image, void* vis_out, void* scratch,
+                                            size_t scratch_bytes, void* stream) {
+    if (!p || !image || (p->nvis > 0 && !vis_out)) return LMG_EINVAL;
+    if (!scratch_ok(p, LMG_OP_PREDICT, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int N = p->g.N, M = p->M;
+    const size_t cs = cplx_size(p->prec);
+    char* sc = static_cast<char*>(scratch);
+    void* grid = sc;
+    void* tmp = sc + align_up(static_cast<size_t>(N) * N * cs);
+    const bool f64 = p->prec == LMG_F64;
+    // Rows q of the image: correct by h(x_p) h(y_q), zero-pad to N, transform over p, write transposed (tmp N x M).
+    FftArgs a = fft_args(N, -1, p->twiddle);
+    a.nrows = M; a.src = image; a.src_pitch = M; a.in_count = M; a.in_pos = N / 2 - M / 2;
+    a.dst = tmp; a.dst_pitch = M; a.out_count = N; a.out_pos = 0;
+    a.h_in = p->hpix; a.h_row = p->hpix; a.row_off = N / 2 - M / 2;
+    {
+        TraceScope ts("fft_rows_forward_correct_pad", s);
+        LMG_HIP(launch_fft_pass(f64, a, s));
+    }
+    // Rows n of tmp: zero-pad to N, transform over q, write grid[m][n].
+    FftArgs b = fft_args(N, -1, p->twiddle);
+    b.nrows = N; b.src = tmp; b.src_pitch = M; b.in_count = M; b.in_pos = N / 2 - M / 2;
+    b.dst = grid; b.dst_pitch = N; b.out_count = N; b.out_pos = 0;
+    {
+        TraceScope ts("fft_cols_forward", s);
+        LMG_HIP(launch_fft_pass(f64, b, s));
+    }
+    return run_degrid(p, grid, vis_out, s);
+}
+
+lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes) {
+    int M = 0;
+    if (!bytes || W < 1 || W > kMaxW || nvis < 0 || nvis > INT32_MAX || prec < LMG_F32 || prec > LMG_F64 ||
+        op < LMG_OP_GRID || op > LMG_OP_PREDICT || !valid_grid(N, W, x0, &M))
+        return LMG_EINVAL;
+    const int T = choose_tile(N, prec);
+    const Layout L = plan_layout(N, T, nvis, prec, choose_cap());
+    *bytes = L.total + scratch_for(N, W, T, M, L.max_items, prec, op);
+    return LMG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+template <typename F>
+lmg_status one_shot(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv, void* ws,
+                    size_t ws_bytes, void* stream, int op, F&& body) {
+    if (!t) return LMG_EINVAL;
+    size_t need = 0;
+    lmg_status st = lmg_workspace_size(N, t->W, t->x0, nvis, prec, op, &need);
+    if (st != LMG_OK) return st;
+    if (!ws || ws_bytes < need) return LMG_EWORKSPACE;
+    size_t pbytes = 0;
+    lmg_plan_workspace_size(N, t->W, nvis, prec, &pbytes);
+    lmg_plan* p = nullptr;
+    st = lmg_plan_create(t, N, prec, nvis, uv, ws, pbytes, stream, &p);
+    if (st != LMG_OK) return st;
+    st = body(p, static_cast<char*>(ws) + pbytes, ws_bytes - pbytes);
+    lmg_plan_destroy(p);
+    return st;
+}
+}  // namespace
+
+extern "C" {
+
+lmg_status lmg_grid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv, const void* vis,
+                    const float* w, void* grid, void* ws, size_t ws_bytes, void* stream) {
+    return one_shot(t, N, prec, nvis, uv, ws, ws_bytes, stream, LMG_OP_GRID, [&](lmg_plan* p, void* sc, size_t sb) {
+        return lmg_grid_planned(p, vis, w, grid, sc, sb, stream);
+    });
+}
+
+lmg_status lmg_degrid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv, const void* grid,
+                      void* vis_out, void* ws, size_t ws_bytes, void* stream) {
+    return one_shot(t, N, prec, nvis, uv, ws, ws_bytes, stream, LMG_OP_DEGRID, [&](lmg_plan* p, void* sc, size_t sb) {
+        return lmg_degrid_planned(p, grid, vis_out, sc, sb, stream);
+    });
+}
+
+lmg_status lmg_make_dirty_image(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                                const void* vis, const float* w, void* image, void* ws, size_t ws_bytes, void* stream) {
+    return one_shot(t, N, prec, nvis, uv, ws, ws_bytes, stream, LMG_OP_DIRTY, [&](lmg_plan* p, void* sc, size_t sb) {
+        return lmg_make_dirty_image_planned(p, vis, w, image, sc, sb, stream);
+    });
+}
+
+lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
+                                    const void* image, void* vis_out, void* ws, size_t ws_bytes, void* stream) {
+    return one_shot(t, N, prec, nvis, uv, ws, ws_bytes, stream, LMG_OP_PREDICT,
+                    [&](lmg_plan* p, void* sc, size_t sb) {
+                        return lmg_predict_visibilities_planned(p, image, vis_out, sc, sb, stream);
+                    });
+}
+
+lmg_status lmg_fft2_centred(int N, lmg_precision prec, int sign, void* data, void* scratch, void* stream) {
+    if (!is_pow2(N) || N < 2 || N > 8192 || (sign != 1 && sign != -1) || !data || !scratch || prec < LMG_F32 ||
+        prec > LMG_F64)
+        return LMG_EINVAL;
+    if (ensure_attributes() != hipSuccess) return LMG_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool f64 = prec == LMG_F64;
+    const size_t cs = cplx_size(prec);
+    void* tw = static_cast<char*>(scratch) + align_up(static_cast<size_t>(N) * N * cs);
+    if (f64) {
+        if (upload(tw, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
+    } else {
+        if (upload(tw, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
+    }
+    FftArgs a = fft_args(N, sign, tw);
+    a.nrows = N; a.src = data; a.src_pitch = N; a.in_count = N; a.in_pos = 0;
+    a.dst = scratch; a.dst_pitch = N; a.out_count = N; a.out_pos = 0;
+    LMG_HIP(launch_fft_pass(f64, a, s));
+    FftArgs b = a;
+    b.src = scratch; b.dst = data;
+    LMG_HIP(launch_fft_pass(f64, b, s));
+    return LMG_OK;
+}
+
+}  // extern "C"

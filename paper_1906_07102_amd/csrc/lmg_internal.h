@@ -1,0 +1,39 @@
+// Internal definitions shared by the host table code and the HIP kernels.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/lmgrid.h"
+
+namespace lmg {
+
+constexpr int kNg = 32;     // h samples on [0, x0] minus one (App. A)
+constexpr int kMg = 16;     // nu samples in (0, 1/2) (App. A)
+constexpr int kMaxW = 16;
+
+// Largest coefficient table the kernels stage in LDS (bytes).
+constexpr size_t kMaxLdsTableBytes = 32768;
+
+}  // namespace lmg
+
+struct lmg_table {
+    int W = 0;
+    double x0 = 0;
+    int Ms = 0;
+    int degree = 0;
+    double E = 0;                  // integrated misfit of the optimiser (App. A step 4)
+    std::vector<double> h;         // kNg + 1 samples of h on [0, x0]
+    std::vector<double> nodes;     // W x (Ms + 1 + degree)
+    // Device coefficient layout: for interval k in [0, Ms] and tap j,
+    // value(t) = c0 + t (c1 + t (c2 + t c3)) with t = Ms (delta - delta_lo) - k,
+    // stored at [(k * W + j) * 4 + s]. Degree 0 stores the node in c0.
+    std::vector<float> coef32;
+    std::vector<double> coef64;
+};
+
+namespace lmg {
+double delta_low(int W);
+double tap_reference(int W);
+}  // namespace lmg

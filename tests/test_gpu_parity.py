@@ -1,0 +1,267 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Every case feeds both sides the same seeded inputs and the same table (the
+oracle's h and nodes, handed to the library with lmg_table_create_from_nodes).
+Tolerances are relative RMS over the compared outputs: 1e-12 in FP64 and 1e-5
+in FP32 (compensated or not).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import imaging as im
+from oracle import lmtable as lt
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1906_07102_amd as lmg  # noqa: E402
+
+TOL = {lmg.F32: 1e-5, lmg.F32_KAHAN: 1e-5, lmg.F64: 1e-12}
+PRECS = [lmg.F32, lmg.F32_KAHAN, lmg.F64]
+DEV = "cuda:0"
+
+
+def rel_rms(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def ctype(prec):
+    return torch.complex128 if prec == lmg.F64 else torch.complex64
+
+
+def to_dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=DEV, dtype=dtype)
+
+
+_TABLES = {}
+
+
+def tables(W, degree, table_size=300, x0=0.25):
+    key = (W, degree, table_size, x0)
+    if key not in _TABLES:
+        otab, h = lt.make_table(W, x0, table_size, degree)
+        gtab = lmg.Table.from_nodes(W, x0, table_size, degree, h, otab.nodes)
+        _TABLES[key] = (otab, gtab, h)
+    return _TABLES[key]
+
+
+def gpu_grid(gtab, N, uv, vis, w, prec):
+    plan = lmg.Plan(gtab, N, to_dev(uv, torch.float64), prec)
+    g = plan.grid(to_dev(vis, ctype(prec)), None if w is None else to_dev(w, torch.float32))
+    torch.cuda.synchronize()
+    return plan, g.cpu().numpy()
+
+
+def small():
+    c = synth.small_case()
+    return c.uv, c.vis, c.weights, c.extra["model_image"]
+
+
+@pytest.fixture(autouse=True)
+def _reset_env():
+    old = {k: os.environ.get(k) for k in ("LMG_CAP", "LMG_TILE")}
+    yield
+    for k, v in old.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+
+
+# ------------------------------------------------------------- gridding ---
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("W,degree", [(7, 3), (5, 3), (3, 3), (7, 1), (7, 0)])
+def test_grid_small(prec, W, degree):
+    print(f"grid small prec={prec} W={W} d={degree}", flush=True)
+    otab, gtab, h = tables(W, degree)
+    uv, vis, w, _ = small()
+    rng = np.random.default_rng(3)
+    w = rng.uniform(0.2, 2.0, len(vis)).astype(np.float32).astype(np.float64)   # weights are FP32 in every mode
+    _, g = gpu_grid(gtab, 128, uv, vis, w, prec)
+    ref = im.grid(uv, vis, w, 128, otab)
+    assert rel_rms(g, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("cap,tile", [("97", None), ("1", None), ("50", "16")])
+def test_grid_split_items_and_tiles(prec, cap, tile):
+    """Dense tiles split into many work items (down to one visibility each) and other tile sizes."""
+    print(f"grid split prec={prec} cap={cap} tile={tile}", flush=True)
+    os.environ["LMG_CAP"] = cap
+    if tile:
+        os.environ["LMG_TILE"] = tile
+    otab, gtab, _ = tables(7, 3)
+    uv, vis, w, _ = small()
+    plan, g = gpu_grid(gtab, 128, uv, vis, None, prec)
+    assert plan.info()["items"] >= plan.info()["busy_tiles"]
+    assert rel_rms(g, im.grid(uv, vis, None, 128, otab)) < TOL[prec]
+
+
+def test_grid_single_visibility_exact():
+    """One V = 1 at integer (u, v) reproduces the node products exactly in FP64 (Eq. 5)."""
+    otab, gtab, _ = tables(7, 3)
+    uv = np.array([[3.0, -5.0]])
+    _, g = gpu_grid(gtab, 64, uv, np.array([1.0 + 0j]), None, lmg.F64)
+    ref = im.grid(uv, np.array([1.0 + 0j]), None, 64, otab)
+    np.testing.assert_array_equal(g, ref)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_grid_edges_wrap_and_ties(prec):
+    """Footprints crossing the grid edge wrap; exact half-integer and integer coordinates."""
+    otab, gtab, _ = tables(7, 3)
+    N = 64
+    uv = np.array([[31.9, 0.0], [-32.0, -31.7], [31.5, 31.5], [-2.5, 4.0], [0.5, -0.5], [12.0, 13.0],
+                   [-31.999, 31.999], [20.25, -10.75]])
+    rng = np.random.default_rng(4)
+    vis = rng.standard_normal(len(uv)) + 1j * rng.standard_normal(len(uv))
+    _, g = gpu_grid(gtab, N, uv, vis, None, prec)
+    assert rel_rms(g, im.grid(uv, vis, None, N, otab)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_empty_and_non_finite(prec):
+    otab, gtab, _ = tables(7, 3)
+    N = 64
+    plan, g = gpu_grid(gtab, N, np.zeros((0, 2)), np.zeros(0, complex), None, prec)
+    assert np.count_nonzero(g) == 0 and plan.check() == 0
+    uv = np.array([[1.2, 3.4], [np.nan, 0.0], [5.5, np.inf], [-7.1, 2.2]])
+    vis = np.array([1 + 1j, 2 + 0j, 3 + 0j, -1 + 0.5j])
+    plan, g = gpu_grid(gtab, N, uv, vis, None, prec)
+    assert plan.check() == -4 and plan.info()["valid"] == 2
+    keep = [0, 3]
+    assert rel_rms(g, im.grid(uv[keep], vis[keep], None, N, otab)) < TOL[prec]
+    G = np.random.default_rng(5).standard_normal((N, N)) * (1 + 0j)
+    out = plan.degrid(to_dev(G, ctype(prec))).cpu().numpy()
+    assert out[1] == 0 and out[2] == 0
+    assert rel_rms(out[keep], im.degrid(uv[keep], G, otab)) < TOL[prec]
+
+
+# ----------------------------------------------------------- degridding ---
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("W,degree", [(7, 3), (3, 3), (7, 0)])
+def test_degrid_small(prec, W, degree):
+    print(f"degrid small prec={prec} W={W} d={degree}", flush=True)
+    otab, gtab, _ = tables(W, degree)
+    uv, _, _, _ = small()
+    rng = np.random.default_rng(6)
+    G = rng.standard_normal((128, 128)) + 1j * rng.standard_normal((128, 128))
+    plan = lmg.Plan(gtab, 128, to_dev(uv, torch.float64), prec)
+    out = plan.degrid(to_dev(G, ctype(prec))).cpu().numpy()
+    assert rel_rms(out, im.degrid(uv, G, otab)) < TOL[prec]
+
+
+def test_adjoint_identity_gpu():
+    """<grid(V), G> = <V, degrid(G)> on the device in FP64 (Sec. 1: transpose operations)."""
+    _, gtab, _ = tables(7, 3)
+    uv, vis, _, _ = small()
+    rng = np.random.default_rng(7)
+    G = rng.standard_normal((128, 128)) + 1j * rng.standard_normal((128, 128))
+    plan = lmg.Plan(gtab, 128, to_dev(uv, torch.float64), lmg.F64)
+    g = plan.grid(to_dev(vis, torch.complex128)).cpu().numpy()
+    d = plan.degrid(to_dev(G, torch.complex128)).cpu().numpy()
+    lhs, rhs = np.vdot(g, G), np.vdot(vis, d)
+    assert abs(lhs - rhs) < 1e-13 * abs(lhs)
+
+
+# ------------------------------------------------------- images and FFT ---
+@pytest.mark.parametrize("prec", [lmg.F32, lmg.F64])
+@pytest.mark.parametrize("N", [64, 128, 4096])
+def test_fft2_centred(prec, N):
+    rng = np.random.default_rng(N)
+    n = min(N, 512)
+    G = np.zeros((N, N), complex)
+    G[:n, :n] = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    for sign in (+1, -1):
+        d = to_dev(G, ctype(prec))
+        lmg.fft2_centred(d, sign)
+        out = d.cpu().numpy()
+        ref = np.fft.fftshift(np.fft.fft2(np.fft.ifftshift(G))) if sign < 0 else \
+            np.fft.fftshift(np.fft.ifft2(np.fft.ifftshift(G))) * N * N
+        if N <= 128:
+            ref2 = im.centred_fft2(G, sign)
+            assert rel_rms(ref, ref2) < 1e-13
+        assert rel_rms(out, ref) < (2e-6 if prec == lmg.F32 else 1e-13)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_dirty_image_small(prec):
+    otab, gtab, h = tables(7, 3)
+    uv, vis, w, _ = small()
+    plan = lmg.Plan(gtab, 128, to_dev(uv, torch.float64), prec)
+    img = plan.make_dirty_image(to_dev(vis, ctype(prec))).cpu().numpy()
+    ref = im.dirty_from_grid(im.grid(uv, vis, None, 128, otab), lt.correction(h, 7, 0.25, 128), 0.25)
+    assert rel_rms(img, ref) < TOL[prec]
+    if prec == lmg.F64:      # and the DFT misfit bound of Eqs. (7)-(8) holds on the device result
+        pq = np.stack(np.meshgrid(np.arange(-32, 32), np.arange(-32, 32), indexing="xy"), -1).reshape(-1, 2)
+        bound = im.image_misfit_bound(uv, vis, None, 128, otab, lt.correction(h, 7, 0.25, 128), pq)
+        dft = im.dft_dirty_image(uv, vis, None, 128, 0.25)
+        assert np.all(np.abs(dft - img).ravel() ** 2 <= bound * (1 + 1e-9))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_predict_small(prec):
+    otab, gtab, h = tables(7, 3)
+    uv, _, _, model = small()
+    plan = lmg.Plan(gtab, 128, to_dev(uv, torch.float64), prec)
+    out = plan.predict_visibilities(to_dev(model, ctype(prec))).cpu().numpy()
+    ref = im.predict_visibilities(uv, model, 128, 0.25, otab, lt.correction(h, 7, 0.25, 128))
+    assert rel_rms(out, ref) < TOL[prec]
+    truth = im.direct_predict(uv, model, 128, 0.25)
+    assert rel_rms(out, truth) < (3e-5 if prec != lmg.F64 else 1e-6)
+
+
+def test_one_shot_equals_planned():
+    """One-shot calls build the same plan internally; LDS atomics make the summation order (and so the
+    last bits) vary between runs, hence a rounding-level tolerance rather than bitwise equality."""
+    _, gtab, _ = tables(7, 3)
+    uv, vis, _, model = small()
+    duv = to_dev(uv, torch.float64)
+    dv = to_dev(vis, torch.complex128)
+    plan = lmg.Plan(gtab, 128, duv, lmg.F64)
+    assert rel_rms(lmg.grid(gtab, 128, duv, dv).cpu().numpy(), plan.grid(dv).cpu().numpy()) < 1e-14
+    img = to_dev(model, torch.complex128)
+    np.testing.assert_array_equal(lmg.predict_visibilities(gtab, 128, duv, img).cpu().numpy(),
+                                  plan.predict_visibilities(img).cpu().numpy())
+    assert rel_rms(lmg.make_dirty_image(gtab, 128, duv, dv).cpu().numpy(),
+                   plan.make_dirty_image(dv).cpu().numpy()) < 1e-14
+    G = plan.grid(dv)
+    np.testing.assert_array_equal(lmg.degrid(gtab, 128, duv, G).cpu().numpy(), plan.degrid(G).cpu().numpy())
+
+
+# ---------------------------------------------------- full-size sampled ---
+def sample_cells(uv, N, W, n, seed):
+    """Cells inside the data footprint plus a few empty ones."""
+    rng = np.random.default_rng(seed)
+    k = rng.integers(0, len(uv), n)
+    nf = np.ceil(uv[k] - W / 2.0).astype(np.int64) + rng.integers(0, W, (n, 2))
+    cells = [((int(b) + N // 2) % N, (int(a) + N // 2) % N) for a, b in nf]
+    return cells + [(0, 0), (N - 1, N // 2), (N // 2, 5)]
+
+
+@pytest.mark.parametrize("which", ["1m", "16m"])
+def test_full_size_grid_degrid_sampled(which):
+    """Full-size array cases in FP32 (the benchmark configuration): sampled cells and visibilities."""
+    c = synth.array_1m_case(with_vis=False) if which == "1m" else synth.array_16m_case(with_vis=False)
+    print(f"full-size {c.name}", flush=True)
+    otab, gtab, _ = tables(c.W, 3)
+    rng = np.random.default_rng(8)
+    vis = (rng.standard_normal(len(c.uv)) + 1j * rng.standard_normal(len(c.uv))).astype(np.complex64)
+    duv = to_dev(c.uv, torch.float64)
+    plan = lmg.Plan(gtab, c.N, duv, lmg.F32)
+    g = plan.grid(to_dev(vis, torch.complex64))
+    cells = sample_cells(c.uv, c.N, c.W, 24, 9)
+    got = np.array([g[r, cc].item() for r, cc in cells])
+    ref = im.grid_cells(c.uv, vis.astype(np.complex128), None, c.N, otab, cells)
+    assert rel_rms(got, ref) < 1e-5
+    G = np.zeros((c.N, c.N), np.complex64)
+    band = slice(c.N // 4 - 8, 3 * c.N // 4 + 8)
+    G[band, band] = (rng.standard_normal(G[band, band].shape) + 1j * rng.standard_normal(G[band, band].shape))
+    out = plan.degrid(to_dev(G, torch.complex64))
+    k = rng.integers(0, len(c.uv), 2000)
+    assert rel_rms(out[k].cpu().numpy(), im.degrid(c.uv[k], G.astype(np.complex128), otab)) < 1e-5

@@ -1,0 +1,110 @@
+"""Host-side checks of the C-ABI library (no GPU): symbols, table generator, error paths.
+
+The library's C++ table generator is independent of the oracle's (its own LM,
+Cholesky and Gauss-Legendre code); two optimisers agree only to their
+tolerance, so the LM result is compared at the optimiser level and the
+deterministic steps (normal-equation solve, correction) from a shared h.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1906_07102_amd as lmg
+from oracle import lmtable as lt
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lmgrid.h")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(lmg.library_path()), reason="library not built")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lmg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lmg.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+@pytest.mark.parametrize("W", [3, 5, 7])
+def test_table_optimiser_matches_oracle_at_optimiser_level(W):
+    t = lmg.Table.create(W, 0.25, 300, 3)
+    h_lib, _ = t.export()
+    h_or = lt.optimal_h(W, 0.25)
+    E_or = lt.integrated_misfit_coarse(h_or, W, 0.25)
+    assert abs(t.integrated_misfit - E_or) <= 0.01 * E_or
+    assert np.max(np.abs(h_lib / h_or - 1)) < 1e-4
+
+
+def test_table_from_h_matches_oracle_nodes():
+    h = lt.optimal_h(7, 0.25)
+    t = lmg.Table.from_h(7, 0.25, 300, 3, h)
+    _, nodes = t.export()
+    ref = lt.table_nodes(h, 7, 0.25, 42, 3)
+    cond = np.linalg.cond(lt.normal_matrix(h, 7, 0.25))
+    assert np.max(np.abs(nodes - ref)) < 1e-15 * cond * 50
+    d = np.linspace(-0.7, 0.7, 15)
+    np.testing.assert_allclose(t.kernel(d).T, lt.kernel_from_h(h, 7, 0.25, d), atol=1e-15 * cond * 50)
+
+
+@pytest.mark.parametrize("W,N", [(3, 128), (7, 256), (7, 4096)])
+def test_correction_matches_oracle(W, N):
+    h = lt.optimal_h(W, 0.25)
+    t = lmg.Table.from_h(W, 0.25, 300, 3, h)
+    a, b = t.correction(N), lt.correction(h, W, 0.25, N)
+    keep = slice(N // 4, 3 * N // 4)          # the retained field |x| <= x0
+    np.testing.assert_allclose(a[keep], b[keep], rtol=1e-13)
+    # towards |x| = 1/2, c(x) is small and h picks up the rounding of the
+    # ill-conditioned solve (cond(A) ~ 1e4 at W = 7) on each side
+    np.testing.assert_allclose(a, b, rtol=1e-10)
+
+
+def test_map_error_matches_oracle_and_paper_level():
+    h = lt.optimal_h(7, 0.25)
+    t = lmg.Table.from_h(7, 0.25, 300, 3, h)
+    x = np.linspace(0, 0.25, 26)
+    exact, tab = t.map_error(x)
+    ref, _, _, _ = lt.map_error(lambda d: lt.kernel_from_h(h, 7, 0.25, d), 7, x)
+    np.testing.assert_allclose(exact, ref, atol=1e-15)
+    assert np.median(exact) < 3e-14          # the W = 7 level of Sec. 2.2
+    assert np.all(tab >= exact * 0.999)      # a cubic 300-entry table adds error (App. F)
+    assert np.median(tab) < 1e-12
+
+
+def test_from_nodes_roundtrip():
+    tab, h = lt.make_table(5, 0.25, 300, 1)
+    t = lmg.Table.from_nodes(5, 0.25, 300, 1, h, tab.nodes)
+    h2, n2 = t.export()
+    np.testing.assert_array_equal(h2, h)
+    np.testing.assert_array_equal(n2, tab.nodes)
+    assert t.Ms == 60 and t.degree == 1 and t.W == 5
+
+
+@pytest.mark.parametrize("args", [(0, 0.25, 300, 3), (17, 0.25, 300, 3), (7, 0.0, 300, 3), (7, 0.6, 300, 3),
+                                  (7, 0.25, 6, 3), (7, 0.25, 300, 4), (7, 0.25, 300, -1)])
+def test_table_invalid_arguments(args):
+    with pytest.raises(lmg.LmgError) as e:
+        lmg.Table.create(*args)
+    assert e.value.status == -1
+
+
+def test_size_queries_and_invalid_grids():
+    lib = lmg.load()
+    n = ctypes.c_size_t()
+    assert lib.lmg_workspace_size(4096, 7, 0.25, 16777152, lmg.F32, lmg.OP_DIRTY, ctypes.byref(n)) == 0
+    assert n.value > 16777152 * 14
+    for N in (100, 32, 16384):
+        assert lib.lmg_workspace_size(N, 7, 0.25, 10, lmg.F32, lmg.OP_GRID, ctypes.byref(n)) == -1
+    assert lib.lmg_workspace_size(128, 7, 0.2, 10, lmg.F32, lmg.OP_GRID, ctypes.byref(n)) == -1   # 2 x0 N not even int
+    assert lib.lmg_workspace_size(128, 7, 0.25, -1, lmg.F32, lmg.OP_GRID, ctypes.byref(n)) == -1
+    assert lib.lmg_workspace_size(128, 7, 0.25, 10, 3, lmg.OP_GRID, ctypes.byref(n)) == -1
+    assert lib.lmg_plan_create(None, 128, 0, 0, None, None, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert lmg.load().lmg_status_string(-2).decode().startswith("workspace")

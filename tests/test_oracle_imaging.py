@@ -220,3 +220,16 @@ def test_table_rate_trend_nearest_neighbour():
         ours = rms[a] / rms[b]
         theirs = paper[a] / paper[b]
         assert 0.5 * theirs < ours < 2.0 * theirs
+
+
+def test_grid_cells_equals_full_grid(w7):
+    """The sampled-cell form of Eq. (5) used for large-grid checks equals the full scatter."""
+    tab, _ = w7
+    N = 64
+    rng = np.random.default_rng(12)
+    uv = rng.uniform(-34, 34, (500, 2))
+    V = rng.standard_normal(500) + 1j * rng.standard_normal(500)
+    w = rng.uniform(0.1, 2.0, 500)
+    G = im.grid(uv, V, w, N, tab)
+    cells = [(0, 0), (1, 63), (32, 32), (40, 17), (63, 2)]
+    np.testing.assert_allclose(im.grid_cells(uv, V, w, N, tab, cells), [G[r, c] for r, c in cells], rtol=1e-13, atol=1e-13)
