@@ -211,6 +211,10 @@ lmg_status lmg_trace_report(char* buf, size_t len);
 
 const char* lmg_status_string(lmg_status s);
 
+/* Text of the last HIP failure seen by this thread (the call and the HIP
+ * error string), or "" if none. Owned by the library. */
+const char* lmg_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

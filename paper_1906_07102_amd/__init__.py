@@ -35,7 +35,10 @@ class LmgError(RuntimeError):
 
     def __init__(self, status: int, what: str):
         self.status = status
-        super().__init__(f"{what}: {_status_string(status)} ({status})")
+        extra = ""
+        if status == -3:
+            extra = " [" + load().lmg_last_error().decode() + "]"
+        super().__init__(f"{what}: {_status_string(status)} ({status}){extra}")
 
 
 class LibraryMissing(RuntimeError):
@@ -93,6 +96,7 @@ def load():
         "lmg_trace_enable": (I, [I]),
         "lmg_trace_report": (I, [ctypes.c_char_p, Z]),
         "lmg_status_string": (ctypes.c_char_p, [I]),
+        "lmg_last_error": (ctypes.c_char_p, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -312,7 +316,8 @@ class Plan:
         if out is None:
             out = torch.empty(self.nvis, dtype=self._vis_dtype(), device=self.device)
         _check_tensor(out, "vis_out", self._vis_dtype(), (self.nvis,), self.device)
-        _check(self.lib.lmg_degrid_planned(self._h, _ptr(grid), _ptr(out), ctypes.c_void_p(0), 0,
+        sc = self.scratch(OP_DEGRID)
+        _check(self.lib.lmg_degrid_planned(self._h, _ptr(grid), _ptr(out), _ptr(sc), sc.numel(),
                                            _stream_handle(stream)), "lmg_degrid_planned")
         return out
 

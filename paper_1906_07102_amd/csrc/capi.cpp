@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -38,9 +39,13 @@ struct lmg_plan {
     int* item_start = nullptr;
     int* cursor = nullptr;
     int4* items = nullptr;
-    int* perm = nullptr;
-    uint16_t* loc = nullptr;
-    void* dlt = nullptr;
+    int* inv0 = nullptr;           // caller index -> tile-order position (-1: dropped)
+    uint16_t* loc0 = nullptr;      // first-tap cell within the tile, by position
+    void* dlt0 = nullptr;          // offsets, by position
+    void* dlt = nullptr;           // offsets, by entry (cell order within items)
+    int* pos2 = nullptr;           // position -> entry
+    int* inv = nullptr;            // caller index -> entry (-1: dropped)
+    int2* pieces = nullptr;
     void* coef = nullptr;
     void* twiddle = nullptr;
     void* hpix = nullptr;
@@ -48,9 +53,17 @@ struct lmg_plan {
 
 namespace {
 
-#define LMG_HIP(call)                                  \
-    do {                                               \
-        if ((call) != hipSuccess) return LMG_EHIP;     \
+thread_local char g_last_error[256] = "";
+
+lmg_status hip_failed(hipError_t e, const char* what, int line) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s (capi.cpp:%d): %s", what, line, hipGetErrorString(e));
+    return LMG_EHIP;
+}
+
+#define LMG_HIP(call)                                                  \
+    do {                                                               \
+        const hipError_t lmg_e_ = (call);                              \
+        if (lmg_e_ != hipSuccess) return hip_failed(lmg_e_, #call, __LINE__); \
     } while (0)
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -65,7 +78,8 @@ int env_int(const char* name, int fallback) {
 }
 
 int choose_tile(int N, lmg_precision prec) {
-    int T = env_int("LMG_TILE", prec == LMG_F32 ? 64 : 32);
+    int T = env_int("LMG_TILE", 32);
+    (void)prec;
     if (!is_pow2(T) || T < 8) T = 32;
     T = std::min(T, 128);
     while (T > N) T /= 2;
@@ -73,20 +87,29 @@ int choose_tile(int N, lmg_precision prec) {
     return T;
 }
 
-int choose_cap() { return env_int("LMG_CAP", 8192); }
+// Largest tile <= T whose LDS patch and table fit one workgroup.
+int fit_tile(int T, int N, lmg_precision prec, int W, int Ms) {
+    while (T > 8 && grid_lds_bytes(prec, W, T, Ms) > kMaxLds && N / (T / 2) <= 128) T /= 2;
+    return T;
+}
+
+int choose_cap() { return std::min(env_int("LMG_CAP", 8192), kMaxCap); }
 
 size_t real_size(lmg_precision p) { return p == LMG_F64 ? 8 : 4; }
 size_t cplx_size(lmg_precision p) { return 2 * real_size(p); }
 size_t patch_cell_size(lmg_precision p) { return p == LMG_F32 ? 8 : 16; }
 
 struct Layout {
-    size_t flags, tile_count, tile_start, item_start, cursor, items, perm, loc, dlt, coef, twiddle, hpix, total;
+    size_t flags, tile_count, tile_start, item_start, cursor, items, inv0, loc0, dlt0, dlt, pos2, inv, pieces, coef,
+        twiddle, hpix, total;
     int max_items;
 };
 
-Layout plan_layout(int N, int T, int64_t nvis, lmg_precision prec, int cap) {
+// Tile arrays are sized for the smallest tile any plan may pick (N / T <= 128,
+// T >= 8), so the size query need not know the table.
+Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap) {
     Layout L{};
-    const int64_t ntiles = static_cast<int64_t>(N / T) * (N / T);
+    const int64_t ntiles = std::min<int64_t>(16384, static_cast<int64_t>(N / 8) * (N / 8));
     L.max_items = static_cast<int>(std::min<int64_t>(ntiles, nvis) + (nvis + cap - 1) / cap + 1);
     size_t o = 0;
     auto take = [&o](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
@@ -96,9 +119,13 @@ Layout plan_layout(int N, int T, int64_t nvis, lmg_precision prec, int cap) {
     L.item_start = take((ntiles + 1) * sizeof(int));
     L.cursor = take(ntiles * sizeof(int));
     L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
-    L.perm = take(static_cast<size_t>(nvis) * sizeof(int));
-    L.loc = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
+    L.inv0 = take(static_cast<size_t>(nvis) * sizeof(int));
+    L.loc0 = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
+    L.dlt0 = take(static_cast<size_t>(nvis) * cplx_size(prec));
     L.dlt = take(static_cast<size_t>(nvis) * cplx_size(prec));
+    L.pos2 = take(static_cast<size_t>(nvis) * sizeof(int));
+    L.inv = take(static_cast<size_t>(nvis) * sizeof(int));
+    L.pieces = take(static_cast<size_t>(nvis) * sizeof(int2));
     L.coef = take(kMaxLdsTableBytes * 2);
     L.twiddle = take(static_cast<size_t>(N) * cplx_size(prec));
     L.hpix = take(static_cast<size_t>(N) * real_size(prec));
@@ -106,18 +133,30 @@ Layout plan_layout(int N, int T, int64_t nvis, lmg_precision prec, int cap) {
     return L;
 }
 
-size_t scratch_for(int N, int W, int T, int M, int items, lmg_precision prec, int op) {
+// Scratch of a planned call: [grid][fft tmp][visibilities in plan order][patches].
+struct Scratch {
+    size_t grid, tmp, vs, patches, total;
+};
+
+Scratch scratch_layout(int N, int W, int T, int M, int items, int64_t nvis, lmg_precision prec, int op) {
     const size_t P = static_cast<size_t>(T + W - 1);
     const size_t patches = align_up(static_cast<size_t>(items) * P * P * patch_cell_size(prec));
     const size_t grid = align_up(static_cast<size_t>(N) * N * cplx_size(prec));
     const size_t tmp = align_up(static_cast<size_t>(M) * N * cplx_size(prec));
-    switch (op) {
-        case LMG_OP_GRID: return patches;
-        case LMG_OP_DEGRID: return 0;
-        case LMG_OP_DIRTY: return grid + tmp + patches;
-        case LMG_OP_PREDICT: return grid + tmp;
-    }
-    return 0;
+    const size_t vs = align_up(static_cast<size_t>(nvis) * cplx_size(prec));
+    Scratch s{};
+    size_t o = 0;
+    const bool image = op == LMG_OP_DIRTY || op == LMG_OP_PREDICT;
+    if (image) { s.grid = o; o += grid; s.tmp = o; o += tmp; }
+    s.vs = o;
+    o += vs;
+    if (op == LMG_OP_GRID || op == LMG_OP_DIRTY) { s.patches = o; o += patches; }
+    s.total = o;
+    return s;
+}
+
+size_t scratch_for(int N, int W, int T, int M, int items, int64_t nvis, lmg_precision prec, int op) {
+    return scratch_layout(N, W, T, M, items, nvis, prec, op).total;
 }
 
 bool valid_grid(int N, int W, double x0, int* M) {
@@ -174,13 +213,18 @@ lmg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     return LMG_OK;
 }
 
-lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* patches, hipStream_t s) {
+lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
+                    hipStream_t s) {
     const lmg_table* t = p->table;
+    {
+        TraceScope ts("permute_in", s);
+        LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vs, s));
+    }
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
     a.n_items = p->n_items; a.dlo = delta_low(t->W);
-    a.items = p->items; a.perm = p->perm; a.loc = p->loc; a.dlt = p->dlt; a.coef = p->coef;
-    a.vis = vis; a.w = w; a.patches = patches;
+    a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
+    a.vis = vs; a.patches = patches;
     {
         TraceScope ts("grid_items", s);
         LMG_HIP(launch_grid(p->prec, a, s));
@@ -193,16 +237,19 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     return LMG_OK;
 }
 
-lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, hipStream_t s) {
+lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, hipStream_t s) {
     const lmg_table* t = p->table;
-    if (p->bad_data && p->nvis > 0) LMG_HIP(hipMemsetAsync(vis_out, 0, static_cast<size_t>(p->nvis) * cplx_size(p->prec), s));
     DegridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
     a.n_items = p->n_items; a.dlo = delta_low(t->W);
-    a.items = p->items; a.perm = p->perm; a.loc = p->loc; a.dlt = p->dlt; a.coef = p->coef;
-    a.grid = grid; a.vis_out = vis_out;
-    TraceScope ts("degrid_items", s);
-    LMG_HIP(launch_degrid(p->prec, a, s));
+    a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
+    a.grid = grid; a.vis_out = vs;
+    {
+        TraceScope ts("degrid_items", s);
+        LMG_HIP(launch_degrid(p->prec, a, s));
+    }
+    TraceScope ts("permute_out", s);
+    LMG_HIP(launch_permute_out(p->prec == LMG_F64, vs, p->inv, p->nvis, vis_out, s));
     return LMG_OK;
 }
 
@@ -214,8 +261,12 @@ FftArgs fft_args(int N, int sign, const void* tw) {
     return f;
 }
 
+Scratch plan_scratch(const lmg_plan* p, int op) {
+    return scratch_layout(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->nvis, p->prec, op);
+}
+
 bool scratch_ok(const lmg_plan* p, int op, void* scratch, size_t bytes) {
-    const size_t need = scratch_for(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->prec, op);
+    const size_t need = plan_scratch(p, op).total;
     return need == 0 || (scratch && bytes >= need);
 }
 
@@ -227,7 +278,7 @@ lmg_status lmg_plan_workspace_size(int N, int W, int64_t nvis, lmg_precision pre
     if (!bytes || !is_pow2(N) || N < 64 || N > 8192 || W < 1 || W > kMaxW || nvis < 0 || nvis > INT32_MAX ||
         prec < LMG_F32 || prec > LMG_F64)
         return LMG_EINVAL;
-    *bytes = plan_layout(N, choose_tile(N, prec), nvis, prec, choose_cap()).total;
+    *bytes = plan_layout(N, nvis, prec, choose_cap()).total;
     return LMG_OK;
 }
 
@@ -239,9 +290,10 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
         return LMG_EINVAL;
     const size_t tab_bytes = (prec == LMG_F64 ? table->coef64.size() * 8 : table->coef32.size() * 4);
     if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
-    const int T = choose_tile(N, prec);
+    const int T = fit_tile(choose_tile(N, prec), N, prec, table->W, table->Ms);
+    if (grid_lds_bytes(prec, table->W, T, table->Ms) > kMaxLds) return LMG_ENOTSUP;
     const int cap = choose_cap();
-    const Layout L = plan_layout(N, T, nvis, prec, cap);
+    const Layout L = plan_layout(N, nvis, prec, cap);
     if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
     if (ensure_attributes() != hipSuccess) return LMG_EHIP;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -262,9 +314,13 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
     p->item_start = reinterpret_cast<int*>(base + L.item_start);
     p->cursor = reinterpret_cast<int*>(base + L.cursor);
     p->items = reinterpret_cast<int4*>(base + L.items);
-    p->perm = reinterpret_cast<int*>(base + L.perm);
-    p->loc = reinterpret_cast<uint16_t*>(base + L.loc);
+    p->inv0 = reinterpret_cast<int*>(base + L.inv0);
+    p->loc0 = reinterpret_cast<uint16_t*>(base + L.loc0);
+    p->dlt0 = base + L.dlt0;
     p->dlt = base + L.dlt;
+    p->pos2 = reinterpret_cast<int*>(base + L.pos2);
+    p->inv = reinterpret_cast<int*>(base + L.inv);
+    p->pieces = reinterpret_cast<int2*>(base + L.pieces);
     p->coef = base + L.coef;
     p->twiddle = base + L.twiddle;
     p->hpix = base + L.hpix;
@@ -296,8 +352,17 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
     }
     {
         TraceScope ts("plan_scatter", s);
-        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->cursor, p->perm, p->loc,
-                                    p->dlt, s));
+        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->cursor, p->inv0, p->loc0,
+                                    p->dlt0, s));
+    }
+    {
+        TraceScope ts("plan_sort_items", s);
+        LMG_HIP(launch_plan_sort(prec == LMG_F64, p->g, p->items, L.max_items, p->flags, p->loc0, p->dlt0, p->dlt,
+                                 p->pos2, p->pieces, s));
+    }
+    {
+        TraceScope ts("plan_compose", s);
+        LMG_HIP(launch_plan_compose(p->inv0, p->pos2, nvis, p->inv, s));
     }
     int flags[4] = {0, 0, 0, 0};
     LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
@@ -310,6 +375,8 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
     *out = p.release();
     return LMG_OK;
 }
+
+const char* lmg_last_error(void) { return g_last_error; }
 
 lmg_status lmg_plan_check(const lmg_plan* p) {
     if (!p) return LMG_EINVAL;
@@ -329,7 +396,7 @@ void lmg_plan_destroy(lmg_plan* p) { delete p; }
 
 lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes) {
     if (!p || !bytes || op < LMG_OP_GRID || op > LMG_OP_PREDICT) return LMG_EINVAL;
-    *bytes = scratch_for(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->prec, op);
+    *bytes = plan_scratch(p, op).total;
     return LMG_OK;
 }
 
@@ -337,15 +404,17 @@ lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, 
                             size_t scratch_bytes, void* stream) {
     if (!p || !grid || (p->nvis > 0 && !vis)) return LMG_EINVAL;
     if (!scratch_ok(p, LMG_OP_GRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
-    return run_grid(p, vis, w, grid, scratch, static_cast<hipStream_t>(stream));
+    const Scratch L = plan_scratch(p, LMG_OP_GRID);
+    char* sc = static_cast<char*>(scratch);
+    return run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, static_cast<hipStream_t>(stream));
 }
 
 lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out, void* scratch, size_t scratch_bytes,
                               void* stream) {
-    (void)scratch;
-    (void)scratch_bytes;
     if (!p || !grid || (p->nvis > 0 && !vis_out)) return LMG_EINVAL;
-    return run_degrid(p, grid, vis_out, static_cast<hipStream_t>(stream));
+    if (!scratch_ok(p, LMG_OP_DEGRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    const Scratch L = plan_scratch(p, LMG_OP_DEGRID);
+    return run_degrid(p, grid, vis_out, static_cast<char*>(scratch) + L.vs, static_cast<hipStream_t>(stream));
 }
 
 lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image, void* scratch,
@@ -354,12 +423,11 @@ lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, cons
     if (!scratch_ok(p, LMG_OP_DIRTY, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int N = p->g.N, M = p->M;
-    const size_t cs = cplx_size(p->prec);
+    const Scratch L = plan_scratch(p, LMG_OP_DIRTY);
     char* sc = static_cast<char*>(scratch);
-    void* grid = sc;
-    void* tmp = sc + align_up(static_cast<size_t>(N) * N * cs);
-    void* patches = static_cast<char*>(tmp) + align_up(static_cast<size_t>(M) * N * cs);
-    lmg_status st = run_grid(p, vis, w, grid, patches, s);
+    void* grid = sc + L.grid;
+    void* tmp = sc + L.tmp;
+    lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, s);
     if (st != LMG_OK) return st;
     const bool f64 = p->prec == LMG_F64;
     // Rows m of the grid: transform over n, keep the central M outputs, write transposed (tmp is M x N).
@@ -386,10 +454,10 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
     if (!scratch_ok(p, LMG_OP_PREDICT, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int N = p->g.N, M = p->M;
-    const size_t cs = cplx_size(p->prec);
+    const Scratch L = plan_scratch(p, LMG_OP_PREDICT);
     char* sc = static_cast<char*>(scratch);
-    void* grid = sc;
-    void* tmp = sc + align_up(static_cast<size_t>(N) * N * cs);
+    void* grid = sc + L.grid;
+    void* tmp = sc + L.tmp;
     const bool f64 = p->prec == LMG_F64;
     // Rows q of the image: correct by h(x_p) h(y_q), zero-pad to N, transform over p, write transposed (tmp N x M).
     FftArgs a = fft_args(N, -1, p->twiddle);
@@ -408,7 +476,7 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
         TraceScope ts("fft_cols_forward", s);
         LMG_HIP(launch_fft_pass(f64, b, s));
     }
-    return run_degrid(p, grid, vis_out, s);
+    return run_degrid(p, grid, vis_out, sc + L.vs, s);
 }
 
 lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes) {
@@ -416,9 +484,11 @@ lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precisi
     if (!bytes || W < 1 || W > kMaxW || nvis < 0 || nvis > INT32_MAX || prec < LMG_F32 || prec > LMG_F64 ||
         op < LMG_OP_GRID || op > LMG_OP_PREDICT || !valid_grid(N, W, x0, &M))
         return LMG_EINVAL;
-    const int T = choose_tile(N, prec);
-    const Layout L = plan_layout(N, T, nvis, prec, choose_cap());
-    *bytes = L.total + scratch_for(N, W, T, M, L.max_items, prec, op);
+    const Layout L = plan_layout(N, nvis, prec, choose_cap());
+    size_t sc = 0;
+    for (int T = 8; T <= 128; T *= 2)          // any tile the plan may settle on
+        if (T <= N && N / T <= 128) sc = std::max(sc, scratch_for(N, W, T, M, L.max_items, nvis, prec, op));
+    *bytes = L.total + sc;
     return LMG_OK;
 }
 
@@ -476,7 +546,7 @@ lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision pre
 }
 
 lmg_status lmg_fft2_centred(int N, lmg_precision prec, int sign, void* data, void* scratch, void* stream) {
-    if (!is_pow2(N) || N < 2 || N > 8192 || (sign != 1 && sign != -1) || !data || !scratch || prec < LMG_F32 ||
+    if (!is_pow2(N) || N < 4 || N > 8192 || (sign != 1 && sign != -1) || !data || !scratch || prec < LMG_F32 ||
         prec > LMG_F64)
         return LMG_EINVAL;
     if (ensure_attributes() != hipSuccess) return LMG_EHIP;

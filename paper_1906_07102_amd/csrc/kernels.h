@@ -11,6 +11,10 @@ namespace lmg {
 
 // Visibilities handled by one block of the plan kernels.
 constexpr int kPlanChunk = 4096;
+// Longest run of one footprint cell handled by one lane (a "piece").
+constexpr int kPiece = 32;
+// Largest work item (visibilities); bounded by the 16-bit in-item offsets.
+constexpr int kMaxCap = 16384;
 
 struct PlanGeom {
     int N;        // grid size
@@ -24,13 +28,11 @@ struct PlanGeom {
 struct GridArgs {
     int N, W, T, ntx, Ms, degree, n_items;
     double dlo;
-    const int4* items;
-    const int* perm;
-    const uint16_t* loc;
-    const void* dlt;       // float2 or double2 offsets, plan order
+    const int4* items;     // (tile, first position, count, pieces)
+    const int2* pieces;    // (first entry, length | cell << 16)
+    const void* dlt;       // float2 or double2 offsets, entry order
     const void* coef;      // coefficient table, float or double
-    const void* vis;       // complex, caller order
-    const float* w;        // caller order or nullptr
+    const void* vis;       // complex, entry order, weights applied
     void* patches;         // n_items patches of (T + W - 1)^2 cells
 };
 
@@ -45,12 +47,11 @@ struct DegridArgs {
     int N, W, T, ntx, Ms, degree, n_items;
     double dlo;
     const int4* items;
-    const int* perm;
-    const uint16_t* loc;
+    const int2* pieces;
     const void* dlt;
     const void* coef;
     const void* grid;
-    void* vis_out;
+    void* vis_out;         // entry order
 };
 
 struct FftArgs {
@@ -75,12 +76,22 @@ hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, 
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int* cursor,
                             int4* items, int* flags, int cap, hipStream_t s);
 hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               int* cursor, int* perm, uint16_t* loc, void* dlt, hipStream_t s);
+                               int* cursor, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s);
+hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
+                            const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
+                            hipStream_t s);
+hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s);
+hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const int* inv, int64_t nvis, void* vs,
+                             hipStream_t s);
+hipError_t launch_permute_out(bool f64, const void* vs, const int* inv, int64_t nvis, void* out, hipStream_t s);
 hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s);
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s);
 hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s);
 hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s);
 int fft_rows_per_block(int N, bool f64);
 hipError_t set_kernel_attributes();
+// LDS bytes of the gridding kernel (the degridding kernel needs no more).
+size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms);
+constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace lmg

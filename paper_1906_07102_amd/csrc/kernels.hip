@@ -6,12 +6,18 @@
 // transpose (Sec. 1, Sec. 5). The tabulated kernel is read with nearest-node
 // or Newton forward interpolation (App. E-F).
 //
-// Work decomposition (see the plan kernels below): visibilities are
-// counting-sorted by uv tile of T x T cells; every work item (a tile, or a
-// slice of a dense tile) is one workgroup that accumulates a
-// (T + W - 1)^2 patch in LDS and writes it out; an assemble kernel adds the
-// patches of each tile and of the three neighbours whose halos overlap it,
-// in a fixed order, and writes every grid cell exactly once.
+// Work decomposition. The plan (built once per uv set) counting-sorts the
+// visibilities by uv tile of T x T cells and splits dense tiles into work
+// items of at most `cap` visibilities. Inside an item the visibilities are
+// ordered by footprint cell (the first tap cell, which fixes all W x W taps)
+// and cut into "pieces": at most kPiece visibilities of one cell. A lane
+// takes one piece, keeps the W x W sums (gridding) or the W x W grid values
+// (degridding) of that cell in registers for the whole piece, and touches
+// LDS once per piece; all lanes of a wave do so together. Each item
+// accumulates a (T + W - 1)^2 patch in LDS and writes it out; the assemble
+// kernel adds the patches of each tile and of the three neighbours whose
+// halos overlap it, in a fixed order, writing every grid cell exactly once.
+// Visibility data are permuted once per call into this entry order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -59,6 +65,8 @@ __device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int d
         out[j] = q[0] + t * (q[1] + t * (q[2] + t * q[3]));
     }
 }
+
+__device__ __forceinline__ int cell_of(int loc, int T) { return (loc >> 8) * T + (loc & 255); }
 
 // ---------------------------------------------------------------- plan
 // Pass 1: validate coordinates and count visibilities per tile.
@@ -142,12 +150,13 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
     if (busy) atomicAdd(&flags[3], busy);
 }
 
-// Pass 3: scatter each visibility to its tile slot; store its local cell and offsets.
+// Pass 3: give each visibility its tile-order position; store its local
+// first-tap cell and offsets there, and the position under its caller index.
 template <typename R>
 __global__ __launch_bounds__(256) void k_plan_scatter(const double2* __restrict__ uv, int64_t nvis, PlanGeom g,
                                                       const int* __restrict__ tile_start, int* __restrict__ tile_cursor,
-                                                      int* __restrict__ perm, uint16_t* __restrict__ loc,
-                                                      typename C2<R>::T* __restrict__ dlt) {
+                                                      int* __restrict__ inv, uint16_t* __restrict__ loc0,
+                                                      typename C2<R>::T* __restrict__ dlt0) {
     extern __shared__ int hist[];
     for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) hist[t] = 0;
     __syncthreads();
@@ -165,6 +174,8 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const double2* __restrict_
             if (tap_geometry(c.x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c.y, g.W, g.ref, g.N, &cv, &dv)) {
                 tile[q] = (cv / g.T) * g.ntx + (cu / g.T);
                 rank[q] = atomicAdd(&hist[tile[q]], 1);
+            } else {
+                inv[k] = -1;                       // dropped: no position
             }
         }
     }
@@ -184,105 +195,390 @@ __global__ __launch_bounds__(256) void k_plan_scatter(const double2* __restrict_
         tap_geometry(c.x, g.W, g.ref, g.N, &cu, &du);
         tap_geometry(c.y, g.W, g.ref, g.N, &cv, &dv);
         const int dst = hist[tile[q]] + rank[q];
-        perm[dst] = static_cast<int>(k);
-        loc[dst] = static_cast<uint16_t>(((cv % g.T) << 8) | (cu % g.T));
+        inv[k] = dst;
+        loc0[dst] = static_cast<uint16_t>(((cv % g.T) << 8) | (cu % g.T));
         typename C2<R>::T d;
         d.x = static_cast<R>(du);
         d.y = static_cast<R>(dv);
-        dlt[dst] = d;
+        dlt0[dst] = d;
     }
 }
 
-// ------------------------------------------------------------ gridding
-// Accumulation policies for the LDS patch.
-struct AccF32 {
-    using Cell = float2;      // (re, im)
-    __device__ static void zero(Cell* c) { *c = make_float2(0.f, 0.f); }
-    __device__ static void add(Cell* c, float re, float im) {
-        atomicAdd(&c->x, re);
-        atomicAdd(&c->y, im);
+// Pass 4 (one workgroup per item): order the item's visibilities by
+// footprint cell (counting sort in LDS) and cut each cell's run into pieces
+// of at most kPiece. Full pieces come first, interleaved over cells (all
+// first pieces of every cell, then all second pieces, ...) so that lanes of
+// one wave hold different cells; then the shorter tails, longest first, so
+// that a wave's lanes run loops of similar length. items[i].w receives the
+// number of pieces; the pieces occupy pieces[item start ...].
+template <typename R>
+__global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __restrict__ items,
+                                                         const int* __restrict__ flags,
+                                                         const uint16_t* __restrict__ loc0,
+                                                         const typename C2<R>::T* __restrict__ dlt0,
+                                                         typename C2<R>::T* __restrict__ dlt,
+                                                         int* __restrict__ pos2, int2* __restrict__ pieces) {
+    if (static_cast<int>(blockIdx.x) >= flags[1]) return;
+    extern __shared__ int sm[];
+    __shared__ int part[256];
+    __shared__ int qcnt[kMaxCap / kPiece + 1];
+    __shared__ int lcnt[kPiece];
+    const int TT = g.T * g.T;
+    int* hist = sm;            // per-cell counts
+    int* cst = sm + TT;        // per-cell start offsets, then scatter cursors
+    const int4 it = items[blockIdx.x];
+    for (int c = threadIdx.x; c < TT; c += blockDim.x) hist[c] = 0;
+    for (int q = threadIdx.x; q < kMaxCap / kPiece + 1; q += blockDim.x) qcnt[q] = 0;
+    if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int e = threadIdx.x; e < it.z; e += blockDim.x) atomicAdd(&hist[cell_of(loc0[it.y + e], g.T)], 1);
+    __syncthreads();
+    const int seg = (TT + blockDim.x - 1) / blockDim.x;
+    const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
+    int sum = 0;
+    for (int c = c0; c < c1; ++c) sum += hist[c];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {       // inclusive scan of the 256 partial sums
+        const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
     }
+    int run = part[threadIdx.x] - sum;
+    for (int c = c0; c < c1; ++c) {
+        cst[c] = run;
+        run += hist[c];
+        const int f = hist[c] / kPiece, t = hist[c] % kPiece;
+        for (int q = 0; q < f; ++q) atomicAdd(&qcnt[q], 1);
+        if (t) atomicAdd(&lcnt[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {                          // piece slots: full by level, then tails by length
+        int a = 0;
+        for (int q = 0; q < kMaxCap / kPiece + 1; ++q) {
+            const int x = qcnt[q];
+            qcnt[q] = a;
+            a += x;
+        }
+        for (int l = kPiece - 1; l >= 1; --l) {
+            const int x = lcnt[l];
+            lcnt[l] = a;
+            a += x;
+        }
+        items[blockIdx.x].w = a;
+    }
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+        const int n = hist[c];
+        if (!n) continue;
+        const int f = n / kPiece, t = n % kPiece;
+        const int start = it.y + cst[c];
+        const int lc = ((c / g.T) << 8) | (c % g.T);
+        for (int q = 0; q < f; ++q)
+            pieces[it.y + atomicAdd(&qcnt[q], 1)] = make_int2(start + q * kPiece, kPiece | (lc << 16));
+        if (t) pieces[it.y + atomicAdd(&lcnt[t], 1)] = make_int2(start + f * kPiece, t | (lc << 16));
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
+        const int dst = it.y + atomicAdd(&cst[cell_of(loc0[it.y + e], g.T)], 1);
+        dlt[dst] = dlt0[it.y + e];
+        pos2[it.y + e] = dst;
+    }
+}
+
+// Pass 5: caller index -> entry index, composed once so that the per-call
+// permutations need a single lookup: inv[k] = pos2[inv0[k]].
+__global__ __launch_bounds__(256) void k_plan_compose(const int* __restrict__ inv0, const int* __restrict__ pos2,
+                                                      int64_t nvis, int* __restrict__ inv) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nvis) return;
+    const int p = inv0[k];
+    inv[k] = p < 0 ? -1 : pos2[p];
+}
+
+// Caller order -> entry order: vs[inv[k]] = w_k V_k. Reads are sequential;
+// the writes of one block land in a few runs per footprint cell.
+template <typename R>
+__global__ __launch_bounds__(256) void k_permute_in(const typename C2<R>::T* __restrict__ vis, const float* __restrict__ w,
+                                                    const int* __restrict__ inv, int64_t nvis,
+                                                    typename C2<R>::T* __restrict__ vs) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nvis) return;
+    const int d = inv[k];
+    if (d < 0) return;
+    typename C2<R>::T v = vis[k];
+    if (w) {
+        const R wk = static_cast<R>(w[k]);
+        v.x *= wk;
+        v.y *= wk;
+    }
+    vs[d] = v;
+}
+
+// Entry order -> caller order: out[k] = vs[inv[k]], zero for dropped visibilities.
+template <typename R>
+__global__ __launch_bounds__(256) void k_permute_out(const typename C2<R>::T* __restrict__ vs, const int* __restrict__ inv,
+                                                     int64_t nvis, typename C2<R>::T* __restrict__ out) {
+    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= nvis) return;
+    const int d = inv[k];
+    typename C2<R>::T v;
+    v.x = 0;
+    v.y = 0;
+    if (d >= 0) v = vs[d];
+    out[k] = v;
+}
+
+// ------------------------------------------------------------ gridding
+// Accumulation policies. `Reg` accumulates one footprint cell over a piece
+// in registers; `Cell` is the LDS patch element. Patches are private to a
+// wave, so a flush is a plain read-modify-write. Lanes of one wave may flush
+// overlapping footprints, so one tap's store must reach LDS before another
+// tap's load: the patch is accessed with 64-bit atomic loads and stores of
+// wavefront scope and sequential consistency, which the compiler neither
+// merges nor reorders (LDS executes one wave's operations in order, so they
+// cost no waits). `merge` adds the wave patches of a workgroup in FP64.
+using u64 = unsigned long long;
+
+__device__ __forceinline__ u64 lds_ld(const void* p) {
+    return __hip_atomic_load(reinterpret_cast<const u64*>(p), __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ void lds_st(void* p, u64 v) {
+    __hip_atomic_store(reinterpret_cast<u64*>(p), v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+__device__ __forceinline__ float2 as_f2(u64 v) {
+    float2 f;
+    __builtin_memcpy(&f, &v, 8);
+    return f;
+}
+__device__ __forceinline__ u64 as_u64(float2 f) {
+    u64 v;
+    __builtin_memcpy(&v, &f, 8);
+    return v;
+}
+__device__ __forceinline__ double as_d(u64 v) { return __builtin_bit_cast(double, v); }
+__device__ __forceinline__ u64 as_u64(double d) { return __builtin_bit_cast(u64, d); }
+
+struct AccF32 {
+    using Cell = float2;
+    using Reg = float2;
+    __device__ static void zero_cell(Cell* c) { *c = make_float2(0.f, 0.f); }
+    __device__ static void zero(Reg& r) { r = make_float2(0.f, 0.f); }
+    __device__ static void add(Reg& r, float re, float im) {
+        r.x += re;
+        r.y += im;
+    }
+    __device__ static void rmw(Cell* c, const Reg& r) {
+        float2 v = as_f2(lds_ld(c));
+        v.x += r.x;
+        v.y += r.y;
+        lds_st(c, as_u64(v));
+    }
+    __device__ static void merge(double& re, double& im, const Cell& c) {
+        re += c.x;
+        im += c.y;
+    }
+    __device__ static Cell out(double re, double im) { return make_float2(static_cast<float>(re), static_cast<float>(im)); }
 };
 
-// Compensated FP32: an atomic add that returns the old value lets the lane
-// recover the rounding error of that very addition exactly (Knuth's TwoSum),
-// which it then adds to a companion compensation cell.
+// Compensated FP32 (Kahan). Registers hold (s, c) pairs per component with
+// value s - c. The flush adds s to the patch sum exactly (Knuth's TwoSum
+// gives the rounding error of that addition), and the error together with
+// the register compensation to the patch's compensation term. A cell's value
+// is sum + comp; the wave patches are merged in FP64 and written as a
+// (high, low) float pair.
 struct AccKahan {
     using Cell = float4;      // (sum re, sum im, comp re, comp im)
-    __device__ static void zero(Cell* c) { *c = make_float4(0.f, 0.f, 0.f, 0.f); }
-    __device__ static void add1(float* s, float* comp, float x) {
-        const float old = atomicAdd(s, x);
-        const float sum = old + x;
-        const float bp = sum - old;
-        const float err = (old - (sum - bp)) + (x - bp);
-        atomicAdd(comp, err);
+    using Reg = float4;       // (s re, s im, c re, c im)
+    __device__ static void zero_cell(Cell* c) { *c = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static void zero(Reg& r) { r = make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static void kahan(float& s, float& c, float x) {
+        const float y = x - c;
+        const float t = s + y;
+        c = (t - s) - y;
+        s = t;
     }
-    __device__ static void add(Cell* c, float re, float im) {
-        add1(&c->x, &c->z, re);
-        add1(&c->y, &c->w, im);
+    __device__ static void add(Reg& r, float re, float im) {
+        kahan(r.x, r.z, re);
+        kahan(r.y, r.w, im);
+    }
+    __device__ static void two_sum(float a, float b, float& s, float& e) {
+        s = a + b;
+        const float bp = s - a;
+        e = (a - (s - bp)) + (b - bp);
+    }
+    __device__ static void rmw(Cell* c, const Reg& r) {
+        float2* h = reinterpret_cast<float2*>(c);
+        const float2 s = as_f2(lds_ld(h));
+        const float2 k = as_f2(lds_ld(h + 1));
+        float nx, ex, ny, ey;
+        two_sum(s.x, r.x, nx, ex);
+        two_sum(s.y, r.y, ny, ey);
+        lds_st(h, as_u64(make_float2(nx, ny)));
+        lds_st(h + 1, as_u64(make_float2(k.x + (ex - r.z), k.y + (ey - r.w))));
+    }
+    __device__ static void merge(double& re, double& im, const Cell& c) {
+        re += static_cast<double>(c.x) + static_cast<double>(c.z);
+        im += static_cast<double>(c.y) + static_cast<double>(c.w);
+    }
+    __device__ static Cell out(double re, double im) {
+        const float hr = static_cast<float>(re), hi = static_cast<float>(im);
+        return make_float4(hr, hi, static_cast<float>(re - hr), static_cast<float>(im - hi));
     }
 };
 
 struct AccF64 {
     using Cell = double2;
-    __device__ static void zero(Cell* c) { *c = make_double2(0.0, 0.0); }
-    __device__ static void add(Cell* c, double re, double im) {
-        atomicAdd(&c->x, re);
-        atomicAdd(&c->y, im);
+    using Reg = double2;
+    __device__ static void zero_cell(Cell* c) { *c = make_double2(0.0, 0.0); }
+    __device__ static void zero(Reg& r) { r = make_double2(0.0, 0.0); }
+    __device__ static void add(Reg& r, double re, double im) {
+        r.x += re;
+        r.y += im;
     }
+    __device__ static void rmw(Cell* c, const Reg& r) {
+        double* d = reinterpret_cast<double*>(c);
+        const double x = as_d(lds_ld(d));
+        const double y = as_d(lds_ld(d + 1));
+        lds_st(d, as_u64(x + r.x));
+        lds_st(d + 1, as_u64(y + r.y));
+    }
+    __device__ static void merge(double& re, double& im, const Cell& c) {
+        re += c.x;
+        im += c.y;
+    }
+    __device__ static Cell out(double re, double im) { return make_double2(re, im); }
 };
 
+// Register accumulation needs W*W accumulators per lane; beyond these widths
+// a piece is flushed after every visibility.
+template <typename Acc, int W>
+struct UseRegs {
+    static constexpr bool value = (sizeof(typename Acc::Reg) == 8) ? (W <= 8) : (W <= 7);
+};
+
+constexpr int kGridWaves = 4;      // waves per gridding workgroup, one private patch each
+
+template <typename Acc, int W>
+__device__ __forceinline__ void flush_piece(typename Acc::Cell* patch, int* owner, int P, int lane, bool have, int l,
+                                            const typename Acc::Reg* acc) {
+    // Lanes holding the same cell take turns: each round one of them wins
+    // the cell (the last store to its owner word) and adds its W x W values.
+    bool pending = have;
+    const int cidx = (l >> 8) * P + (l & 255);
+    while (__any(pending)) {
+        if (pending) __hip_atomic_store(&owner[cidx], lane, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int who = pending ? __hip_atomic_load(&owner[cidx], __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT) : -1;
+        if (pending && who == lane) {
+            typename Acc::Cell* row = patch + cidx;
+#pragma unroll
+            for (int r = 0; r < W; ++r)
+#pragma unroll
+                for (int c = 0; c < W; ++c) Acc::rmw(&row[r * P + c], acc[UseRegs<Acc, W>::value ? r * W + c : 0]);
+            pending = false;
+        }
+    }
+}
+
 template <typename R, typename Acc, int W>
-__global__ __launch_bounds__(256) void k_grid_items(GridArgs a) {
+__global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
+    constexpr bool kRegs = UseRegs<Acc, W>::value;
+    const int P = a.T + W - 1;
+    const int P2 = P * P;
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
-    Cell* patch = reinterpret_cast<Cell*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
-    const int P = a.T + W - 1;
+    Cell* patches = reinterpret_cast<Cell*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
+    int* owners = reinterpret_cast<int*>(patches + kGridWaves * P2);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    Cell* patch = patches + wave * P2;
+    int* owner = owners + wave * P2;
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
-    for (int i = threadIdx.x; i < P * P; i += blockDim.x) Acc::zero(&patch[i]);
+    for (int i = threadIdx.x; i < kGridWaves * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
     __syncthreads();
     const int4 it = a.items[blockIdx.x];
-    const VT* vis = reinterpret_cast<const VT*>(a.vis);
+    const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
     const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
     const R dlo = static_cast<R>(a.dlo);
-    for (int i = it.y + threadIdx.x; i < it.y + it.z; i += blockDim.x) {
-        const int k = a.perm[i];
-        const int l = a.loc[i];
-        const VT d = dlt[i];
-        VT v = vis[k];
-        if (a.w) {
-            const R wk = static_cast<R>(a.w[k]);
-            v.x *= wk;
-            v.y *= wk;
-        }
-        R cu[W], cv[W];
-        weights<R, W>(tab, a.Ms, a.degree, d.x, dlo, cu);
-        weights<R, W>(tab, a.Ms, a.degree, d.y, dlo, cv);
-        Cell* row = patch + (l >> 8) * P + (l & 255);
+    constexpr int kB = 4;                                   // entries whose loads are issued together
+    const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
+    for (int rd = 0; rd < rounds; ++rd) {                   // uniform across the workgroup
+        const int p = rd * blockDim.x + threadIdx.x;
+        const bool have = p < it.w;
+        int2 pc = make_int2(0, 0);
+        if (have) pc = a.pieces[it.y + p];
+        const int len = pc.y & 0xffff;
+        const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
+        typename Acc::Reg acc[kRegs ? W * W : 1];
 #pragma unroll
-        for (int r = 0; r < W; ++r) {
-            const R ar = v.x * cv[r], ai = v.y * cv[r];
+        for (int q = 0; q < (kRegs ? W * W : 1); ++q) Acc::zero(acc[q]);
+        for (int j0 = 0; j0 < len; j0 += kB) {
+            VT dv[kB], vv[kB];
 #pragma unroll
-            for (int c = 0; c < W; ++c) Acc::add(&row[c], ar * cu[c], ai * cu[c]);
-            row += P;
+            for (int u = 0; u < kB; ++u) {
+                if (j0 + u < len) {
+                    dv[u] = dlt[pc.x + j0 + u];
+                    vv[u] = vis[pc.x + j0 + u];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (j0 + u >= len) break;
+                R cu[W], cv[W];
+                weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
+                weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                if constexpr (kRegs) {
+#pragma unroll
+                    for (int r = 0; r < W; ++r) {
+                        const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+#pragma unroll
+                        for (int c = 0; c < W; ++c) Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                    }
+                } else {
+                    // Wide footprints: flush the visibility tap by tap (one register).
+                    Cell* row = patch + (l >> 8) * P + (l & 255);
+#pragma unroll
+                    for (int r = 0; r < W; ++r) {
+                        const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+#pragma unroll
+                        for (int c = 0; c < W; ++c) {
+                            typename Acc::Reg one;
+                            Acc::zero(one);
+                            Acc::add(one, ar * cu[c], ai * cu[c]);
+                            Acc::rmw(&row[r * P + c], one);
+                        }
+                    }
+                }
+            }
         }
+        if constexpr (kRegs) flush_piece<Acc, W>(patch, owner, P, lane, have && len > 0, l, acc);
     }
     __syncthreads();
-    Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(blockIdx.x) * P * P;
-    for (int i = threadIdx.x; i < P * P; i += blockDim.x) out[i] = patch[i];
+    Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(blockIdx.x) * P2;
+    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int w = 0; w < kGridWaves; ++w) Acc::merge(re, im, patches[w * P2 + i]);
+        out[i] = Acc::out(re, im);
+    }
 }
 
 // Sum the patches covering each tile (own tile, left, upper, upper-left
-// neighbours, in that fixed order) and write every grid cell once.
+// neighbours, in that fixed order) and write every grid cell once. One
+// workgroup per kAssembleRows rows of a tile.
+constexpr int kAssembleRows = 8;
+
 template <typename R, typename Acc>
 __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
-    const int t = blockIdx.x;
+    const int nblk = a.T / kAssembleRows;
+    const int t = blockIdx.x / nblk;
+    const int rb = (blockIdx.x % nblk) * kAssembleRows;
     const int tm = t / a.ntx, tn = t % a.ntx;
     const int P = a.T + a.W - 1;
     const int halo = a.W - 1;
@@ -298,13 +594,12 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
         i0[s] = a.item_start[src_t[s]];
         i1[s] = a.item_start[src_t[s] + 1];
     }
-    for (int cell = threadIdx.x; cell < a.T * a.T; cell += blockDim.x) {
-        const int lr = cell / a.T, lc = cell % a.T;
+    for (int cell = threadIdx.x; cell < kAssembleRows * a.T; cell += blockDim.x) {
+        const int lr = rb + cell / a.T, lc = cell % a.T;
         double sr = 0.0, si = 0.0;      // the few partial sums per cell are merged in FP64
         for (int s = 0; s < 4; ++s) {
-            const int pr = lr + src_dr[s], pc = lc + src_dc[s];
-            if (s && (pr >= P || pc >= P)) continue;
             if ((s == 1 && lc >= halo) || (s == 2 && lr >= halo) || (s == 3 && (lr >= halo || lc >= halo))) continue;
+            const int pr = lr + src_dr[s], pc = lc + src_dc[s];
             for (int it = i0[s]; it < i1[s]; ++it) {
                 const Cell c = patches[static_cast<size_t>(it) * P * P + pr * P + pc];
                 sr += static_cast<double>(c.x);
@@ -327,6 +622,7 @@ template <typename R, int W>
 __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     using VT = typename C2<R>::T;
+    constexpr bool kRegs = (sizeof(R) == 4) ? (W <= 8) : (W <= 7);
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
     VT* patch = reinterpret_cast<VT*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
@@ -337,66 +633,94 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     const int tm = it.x / a.ntx, tn = it.x % a.ntx;
     const VT* grid = reinterpret_cast<const VT*>(a.grid);
     for (int i = threadIdx.x; i < P * P; i += blockDim.x) {
-        const int r = i / P, c = i % P;
+        const int r = i / P, c = i - (i / P) * P;
         const int gr = (tm * a.T + r) & (a.N - 1), gc = (tn * a.T + c) & (a.N - 1);
         patch[i] = grid[static_cast<size_t>(gr) * a.N + gc];
     }
     __syncthreads();
-    VT* out = reinterpret_cast<VT*>(a.vis_out);
+    VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
     const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
     const R dlo = static_cast<R>(a.dlo);
-    for (int i = it.y + threadIdx.x; i < it.y + it.z; i += blockDim.x) {
-        const int k = a.perm[i];
-        const int l = a.loc[i];
-        const VT d = dlt[i];
-        R cu[W], cv[W];
-        weights<R, W>(tab, a.Ms, a.degree, d.x, dlo, cu);
-        weights<R, W>(tab, a.Ms, a.degree, d.y, dlo, cv);
+    constexpr int kB = 4;
+    for (int p = threadIdx.x; p < it.w; p += blockDim.x) {
+        const int2 pc = a.pieces[it.y + p];
+        const int len = pc.y & 0xffff;
+        const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
         const VT* row = patch + (l >> 8) * P + (l & 255);
-        R accr = 0, acci = 0;
+        VT pr[kRegs ? W * W : 1];
+        if constexpr (kRegs) {
 #pragma unroll
-        for (int r = 0; r < W; ++r) {
-            R sr = 0, si = 0;
+            for (int r = 0; r < W; ++r)
 #pragma unroll
-            for (int c = 0; c < W; ++c) {
-                const VT gv = row[c];
-                sr += cu[c] * gv.x;
-                si += cu[c] * gv.y;
-            }
-            accr += cv[r] * sr;
-            acci += cv[r] * si;
-            row += P;
+                for (int c = 0; c < W; ++c) pr[r * W + c] = row[r * P + c];
         }
-        VT o;
-        o.x = accr;
-        o.y = acci;
-        out[k] = o;
+        for (int j0 = 0; j0 < len; j0 += kB) {
+            VT dv[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u)
+                if (j0 + u < len) dv[u] = dlt[pc.x + j0 + u];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                if (j0 + u >= len) break;
+                R cu[W], cv[W];
+                weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
+                weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                R accr = 0, acci = 0;
+#pragma unroll
+                for (int r = 0; r < W; ++r) {
+                    R sr = 0, si = 0;
+#pragma unroll
+                    for (int c = 0; c < W; ++c) {
+                        const VT gv = kRegs ? pr[r * W + c] : row[r * P + c];
+                        sr += cu[c] * gv.x;
+                        si += cu[c] * gv.y;
+                    }
+                    accr += cv[r] * sr;
+                    acci += cv[r] * si;
+                }
+                VT o;
+                o.x = accr;
+                o.y = acci;
+                out[pc.x + j0 + u] = o;
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------------ FFT
 // One pass of the centred 2D transform: ROWS rows of `src` are each loaded
 // into an N-point buffer in LDS (`in_count` values placed from position
-// `in_pos`, zeros elsewhere), transformed with a Stockham radix-4/2 FFT of
-// sign `sign`, and the outputs at positions [out_pos, out_pos + out_count)
-// are written transposed into `dst` (dst row = output position, dst column =
-// source row). Centring: input position s is multiplied by (-1)^s and output
-// position r by (-1)^r, so positions are indices shifted by N/2. Optional
-// real factors: h_in[s] on inputs, h_out[r] on outputs, h_row[row + row_off]
-// on a whole row.
-template <typename R, int ROWS>
-__global__ __launch_bounds__(512) void k_fft_pass(FftArgs a) {
+// `in_pos`, zeros elsewhere), transformed with a Stockham radix-4 (plus one
+// radix-2 when log2 N is odd) FFT of sign `sign`, and the outputs at
+// positions [out_pos, out_pos + out_count) are written transposed into `dst`
+// (dst row = output position, dst column = source row). Centring: input
+// position s is multiplied by (-1)^s and output position r by (-1)^r, so
+// positions are indices shifted by N/2. Optional real factors: h_in[s] on
+// inputs, h_out[r] on outputs, h_row[row + row_off] on a whole row.
+template <int N, int ROWS>
+struct FftShape {
+    static constexpr int kLog2 = __builtin_ctz(N);
+    static constexpr int kPass4 = kLog2 / 2;
+    static constexpr bool kPass2 = (kLog2 & 1) != 0;
+    static constexpr int kThreads = (ROWS * N / 4) < 1024 ? (ROWS * N / 4 > 0 ? ROWS * N / 4 : 1) : 1024;
+    static constexpr int kB4 = ROWS * N / 4 / kThreads;   // radix-4 butterflies per thread per pass
+    static constexpr int kB2 = ROWS * N / 2 / kThreads;
+};
+
+template <typename R, int N, int ROWS>
+__global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     using VT = typename C2<R>::T;
+    using S = FftShape<N, ROWS>;
+    constexpr int NT = S::kThreads;
     VT* buf = reinterpret_cast<VT*>(smem);
-    const int N = a.N;
     const int row0 = blockIdx.x * ROWS;
     const VT* src = reinterpret_cast<const VT*>(a.src);
-    const R* tw = reinterpret_cast<const R*>(a.twiddle);   // e^{-2 pi i t / N}, interleaved
+    const VT* tw = reinterpret_cast<const VT*>(a.twiddle);   // (cos, -sin)(2 pi t / N)
     const R* h_in = reinterpret_cast<const R*>(a.h_in);
     const R* h_out = reinterpret_cast<const R*>(a.h_out);
     const R* h_row = reinterpret_cast<const R*>(a.h_row);
-    for (int idx = threadIdx.x; idx < ROWS * N; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < ROWS * N; idx += NT) {
         const int rr = idx / N, s = idx % N;
         const int row = row0 + rr;
         VT v;
@@ -415,59 +739,85 @@ __global__ __launch_bounds__(512) void k_fft_pass(FftArgs a) {
     }
     __syncthreads();
     const R sg = static_cast<R>(a.sign);
-    constexpr int kRegs = 64;     // butterfly outputs a thread holds across the barrier
-    VT hold[kRegs];
-    for (int Ns = 1; Ns < N;) {
-        const int Rp = ((N / Ns) % 4 == 0) ? 4 : 2;
-        const int nb = N / Rp;
-        const int total = ROWS * nb;
-        const int stride = N / (Ns * Rp);
-        int h = 0;
-        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+    int Ns = 1;
+#pragma unroll 1
+    for (int pass = 0; pass < S::kPass4; ++pass) {
+        constexpr int nb = N / 4;
+        const int stride = N / (Ns * 4);
+        VT hold[4 * S::kB4];
+#pragma unroll
+        for (int q = 0; q < S::kB4; ++q) {
+            const int b = threadIdx.x + q * NT;
             const int rr = b / nb, j = b % nb;
-            VT v[4];
             const int jm = j % Ns;
-            for (int r = 0; r < Rp; ++r) {
+            VT v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
                 VT x = buf[rr * N + j + r * nb];
                 if (r) {
-                    const int ti = (r * jm * stride) & (N - 1);
-                    const R c = tw[2 * ti], s = sg < 0 ? tw[2 * ti + 1] : -tw[2 * ti + 1];
-                    const R xr = x.x * c - x.y * s;
-                    x.y = x.x * s + x.y * c;
+                    const VT t = tw[(r * jm * stride) & (N - 1)];
+                    const R c = t.x, sn = -sg * t.y;        // e^{sign i 2 pi r jm / (4 Ns)}
+                    const R xr = x.x * c - x.y * sn;
+                    x.y = x.x * sn + x.y * c;
                     x.x = xr;
                 }
                 v[r] = x;
             }
-            if (Rp == 4) {
-                VT t0, t1, t2, t3;
-                t0.x = v[0].x + v[2].x; t0.y = v[0].y + v[2].y;
-                t1.x = v[0].x - v[2].x; t1.y = v[0].y - v[2].y;
-                t2.x = v[1].x + v[3].x; t2.y = v[1].y + v[3].y;
-                const R dx = v[1].x - v[3].x, dy = v[1].y - v[3].y;
-                t3.x = -sg * dy; t3.y = sg * dx;                 // (v1 - v3) * (sign i)
-                hold[h + 0].x = t0.x + t2.x; hold[h + 0].y = t0.y + t2.y;
-                hold[h + 1].x = t1.x + t3.x; hold[h + 1].y = t1.y + t3.y;
-                hold[h + 2].x = t0.x - t2.x; hold[h + 2].y = t0.y - t2.y;
-                hold[h + 3].x = t1.x - t3.x; hold[h + 3].y = t1.y - t3.y;
-            } else {
-                hold[h + 0].x = v[0].x + v[1].x; hold[h + 0].y = v[0].y + v[1].y;
-                hold[h + 1].x = v[0].x - v[1].x; hold[h + 1].y = v[0].y - v[1].y;
-            }
-            h += Rp;
+            VT t0, t1, t2, t3;
+            t0.x = v[0].x + v[2].x; t0.y = v[0].y + v[2].y;
+            t1.x = v[0].x - v[2].x; t1.y = v[0].y - v[2].y;
+            t2.x = v[1].x + v[3].x; t2.y = v[1].y + v[3].y;
+            const R dx = v[1].x - v[3].x, dy = v[1].y - v[3].y;
+            t3.x = -sg * dy; t3.y = sg * dx;                       // (v1 - v3) (sign i)
+            hold[4 * q + 0].x = t0.x + t2.x; hold[4 * q + 0].y = t0.y + t2.y;
+            hold[4 * q + 1].x = t1.x + t3.x; hold[4 * q + 1].y = t1.y + t3.y;
+            hold[4 * q + 2].x = t0.x - t2.x; hold[4 * q + 2].y = t0.y - t2.y;
+            hold[4 * q + 3].x = t1.x - t3.x; hold[4 * q + 3].y = t1.y - t3.y;
         }
         __syncthreads();
-        h = 0;
-        for (int b = threadIdx.x; b < total; b += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < S::kB4; ++q) {
+            const int b = threadIdx.x + q * NT;
             const int rr = b / nb, j = b % nb;
-            const int dst = (j / Ns) * Ns * Rp + (j % Ns);
-            for (int r = 0; r < Rp; ++r) buf[rr * N + dst + r * Ns] = hold[h + r];
-            h += Rp;
+            const int dst = (j / Ns) * Ns * 4 + (j % Ns);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) buf[rr * N + dst + r * Ns] = hold[4 * q + r];
         }
         __syncthreads();
-        Ns *= Rp;
+        Ns *= 4;
+    }
+    if constexpr (S::kPass2) {
+        constexpr int nb = N / 2;
+        const int stride = N / (Ns * 2);
+        VT hold[2 * S::kB2];
+#pragma unroll
+        for (int q = 0; q < S::kB2; ++q) {
+            const int b = threadIdx.x + q * NT;
+            const int rr = b / nb, j = b % nb;
+            const int jm = j % Ns;
+            const VT x0 = buf[rr * N + j];
+            VT x = buf[rr * N + j + nb];
+            const VT t = tw[(jm * stride) & (N - 1)];
+            const R c = t.x, sn = -sg * t.y;
+            const R xr = x.x * c - x.y * sn;
+            x.y = x.x * sn + x.y * c;
+            x.x = xr;
+            hold[2 * q].x = x0.x + x.x; hold[2 * q].y = x0.y + x.y;
+            hold[2 * q + 1].x = x0.x - x.x; hold[2 * q + 1].y = x0.y - x.y;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < S::kB2; ++q) {
+            const int b = threadIdx.x + q * NT;
+            const int rr = b / nb, j = b % nb;
+            const int dst = (j / Ns) * Ns * 2 + (j % Ns);
+            buf[rr * N + dst] = hold[2 * q];
+            buf[rr * N + dst + Ns] = hold[2 * q + 1];
+        }
+        __syncthreads();
     }
     VT* dst = reinterpret_cast<VT*>(a.dst);
-    for (int idx = threadIdx.x; idx < a.out_count * ROWS; idx += blockDim.x) {
+    for (int idx = threadIdx.x; idx < a.out_count * ROWS; idx += NT) {
         const int o = idx / ROWS, rr = idx % ROWS;
         const int row = row0 + rr;
         if (row >= a.nrows) continue;
@@ -489,12 +839,12 @@ template <typename R, typename Acc, int W>
 hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
-    const size_t shm = tab + static_cast<size_t>(P) * P * sizeof(typename Acc::Cell);
+    const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 4) * dev::kGridWaves;
     static const hipError_t attr = hipFuncSetAttribute(
         reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>), hipFuncAttributeMaxDynamicSharedMemorySize,
         160 * 1024);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(a.n_items), dim3(256), shm, s, a);
+    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(a.n_items), dim3(64 * dev::kGridWaves), shm, s, a);
     return hipGetLastError();
 }
 template <typename R, int W>
@@ -549,17 +899,63 @@ hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_
 }
 
 hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               int* cursor, int* perm, uint16_t* loc, void* dlt, hipStream_t s) {
+                               int* cursor, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s) {
     const int64_t nb = (nvis + kPlanChunk - 1) / kPlanChunk;
     if (nb == 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(static_cast<unsigned>(nb)), dim3(256),
                            g.ntiles * sizeof(int), s, reinterpret_cast<const double2*>(uv), nvis, g, tile_start,
-                           cursor, perm, loc, reinterpret_cast<double2*>(dlt));
+                           cursor, inv, loc0, reinterpret_cast<double2*>(dlt0));
     else
         hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(static_cast<unsigned>(nb)), dim3(256),
                            g.ntiles * sizeof(int), s, reinterpret_cast<const double2*>(uv), nvis, g, tile_start,
-                           cursor, perm, loc, reinterpret_cast<float2*>(dlt));
+                           cursor, inv, loc0, reinterpret_cast<float2*>(dlt0));
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
+                            const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
+                            hipStream_t s) {
+    if (max_items == 0) return hipSuccess;
+    const size_t shm = 2 * static_cast<size_t>(g.T) * g.T * sizeof(int);
+    if (f64)
+        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(max_items), dim3(256), shm, s, g, items, flags, loc0,
+                           reinterpret_cast<const double2*>(dlt0), reinterpret_cast<double2*>(dlt), pos2, pieces);
+    else
+        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(max_items), dim3(256), shm, s, g, items, flags, loc0,
+                           reinterpret_cast<const float2*>(dlt0), reinterpret_cast<float2*>(dlt), pos2, pieces);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s) {
+    if (nvis == 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_plan_compose, dim3(static_cast<unsigned>((nvis + 255) / 256)), dim3(256), 0, s, inv0,
+                       pos2, nvis, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const int* inv, int64_t nvis, void* vs,
+                             hipStream_t s) {
+    if (nvis == 0) return hipSuccess;
+    const unsigned nb = static_cast<unsigned>((nvis + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL(dev::k_permute_in<double>, dim3(nb), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(vis), w, inv, nvis, reinterpret_cast<double2*>(vs));
+    else
+        hipLaunchKernelGGL(dev::k_permute_in<float>, dim3(nb), dim3(256), 0, s,
+                           reinterpret_cast<const float2*>(vis), w, inv, nvis, reinterpret_cast<float2*>(vs));
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_out(bool f64, const void* vs, const int* inv, int64_t nvis, void* out, hipStream_t s) {
+    if (nvis == 0) return hipSuccess;
+    const unsigned nb = static_cast<unsigned>((nvis + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL(dev::k_permute_out<double>, dim3(nb), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(vs), inv, nvis, reinterpret_cast<double2*>(out));
+    else
+        hipLaunchKernelGGL(dev::k_permute_out<float>, dim3(nb), dim3(256), 0, s,
+                           reinterpret_cast<const float2*>(vs), inv, nvis, reinterpret_cast<float2*>(out));
     return hipGetLastError();
 }
 
@@ -574,7 +970,7 @@ hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s) {
-    const unsigned nt = static_cast<unsigned>(a.ntx * a.ntx);
+    const unsigned nt = static_cast<unsigned>(a.ntx * a.ntx * (a.T / dev::kAssembleRows));
     switch (prec) {
         case LMG_F32: hipLaunchKernelGGL((dev::k_assemble<float, dev::AccF32>), dim3(nt), dim3(256), 0, s, a); break;
         case LMG_F32_KAHAN:
@@ -597,38 +993,69 @@ int fft_rows_per_block(int N, bool f64) {
     return rows;
 }
 
-hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s) {
-    const int rows = fft_rows_per_block(a.N, f64);
-    const unsigned nb = static_cast<unsigned>((a.nrows + rows - 1) / rows);
-    if (nb == 0) return hipSuccess;
-    const size_t shm = static_cast<size_t>(rows) * a.N * (f64 ? 16 : 8);
-#define LMG_FFT(R, ROWS) hipLaunchKernelGGL((dev::k_fft_pass<R, ROWS>), dim3(nb), dim3(512), shm, s, a)
-    if (f64) {
-        if (rows == 4) LMG_FFT(double, 4); else if (rows == 2) LMG_FFT(double, 2); else LMG_FFT(double, 1);
-    } else {
-        if (rows == 4) LMG_FFT(float, 4); else if (rows == 2) LMG_FFT(float, 2); else LMG_FFT(float, 1);
-    }
-#undef LMG_FFT
+namespace {
+template <typename R, int N, int ROWS>
+hipError_t launch_fft_nr(const FftArgs& a, hipStream_t s) {
+    using S = dev::FftShape<N, ROWS>;
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&dev::k_fft_pass<R, N, ROWS>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (attr != hipSuccess) return attr;
+    const unsigned nb = static_cast<unsigned>((a.nrows + ROWS - 1) / ROWS);
+    const size_t shm = static_cast<size_t>(ROWS) * N * sizeof(typename dev::C2<R>::T);
+    hipLaunchKernelGGL((dev::k_fft_pass<R, N, ROWS>), dim3(nb), dim3(S::kThreads), shm, s, a);
     return hipGetLastError();
+}
+template <typename R, int N>
+hipError_t launch_fft_n(const FftArgs& a, hipStream_t s) {
+    constexpr size_t row_bytes = static_cast<size_t>(N) * 2 * sizeof(R);
+    constexpr int rows = (4 * row_bytes <= 131072) ? 4 : (2 * row_bytes <= 131072) ? 2 : 1;
+    return launch_fft_nr<R, N, rows>(a, s);
+}
+template <typename R>
+hipError_t launch_fft_t(const FftArgs& a, hipStream_t s) {
+    switch (a.N) {
+        case 4: return launch_fft_n<R, 4>(a, s);
+        case 8: return launch_fft_n<R, 8>(a, s);
+        case 16: return launch_fft_n<R, 16>(a, s);
+        case 32: return launch_fft_n<R, 32>(a, s);
+        case 64: return launch_fft_n<R, 64>(a, s);
+        case 128: return launch_fft_n<R, 128>(a, s);
+        case 256: return launch_fft_n<R, 256>(a, s);
+        case 512: return launch_fft_n<R, 512>(a, s);
+        case 1024: return launch_fft_n<R, 1024>(a, s);
+        case 2048: return launch_fft_n<R, 2048>(a, s);
+        case 4096: return launch_fft_n<R, 4096>(a, s);
+        case 8192: return launch_fft_n<R, 8192>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s) {
+    if (a.nrows == 0) return hipSuccess;
+    return f64 ? launch_fft_t<double>(a, s) : launch_fft_t<float>(a, s);
 }
 
 hipError_t set_kernel_attributes() {
-    // Opt every LDS-heavy kernel in to the full 160 KB of LDS.
-    const int lds = 160 * 1024;
     hipError_t e = hipSuccess;
-#define LMG_ATTR(...) do { hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(__VA_ARGS__), \
-        hipFuncAttributeMaxDynamicSharedMemorySize, lds); if (r != hipSuccess) e = r; } while (0)
-    LMG_ATTR(&dev::k_fft_pass<float, 4>);
-    LMG_ATTR(&dev::k_fft_pass<float, 2>);
-    LMG_ATTR(&dev::k_fft_pass<float, 1>);
-    LMG_ATTR(&dev::k_fft_pass<double, 4>);
-    LMG_ATTR(&dev::k_fft_pass<double, 2>);
-    LMG_ATTR(&dev::k_fft_pass<double, 1>);
-    LMG_ATTR(&dev::k_plan_count);
-    LMG_ATTR(&dev::k_plan_scatter<float>);
-    LMG_ATTR(&dev::k_plan_scatter<double>);
+#define LMG_ATTR(bytes, ...) do { hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(__VA_ARGS__), \
+        hipFuncAttributeMaxDynamicSharedMemorySize, bytes); if (r != hipSuccess) e = r; } while (0)
+    // Per-tile histograms of up to 128 x 128 ints; the item sort keeps two per-cell arrays of up to 128 x 128.
+    LMG_ATTR(64 * 1024, &dev::k_plan_count);
+    LMG_ATTR(64 * 1024, &dev::k_plan_scatter<float>);
+    LMG_ATTR(64 * 1024, &dev::k_plan_scatter<double>);
+    LMG_ATTR(128 * 1024, &dev::k_plan_sort_items<float>);
+    LMG_ATTR(128 * 1024, &dev::k_plan_sort_items<double>);
 #undef LMG_ATTR
     return e;
+}
+
+size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms) {
+    const size_t rs = prec == LMG_F64 ? 8 : 4;
+    const size_t cell = prec == LMG_F32 ? 8 : 16;
+    const size_t tab = ((static_cast<size_t>(Ms + 1) * W * 4 * rs) + 15) & ~size_t(15);
+    const size_t P = static_cast<size_t>(T + W - 1);
+    return tab + P * P * (cell + 4) * dev::kGridWaves;
 }
 
 }  // namespace lmg

@@ -3,6 +3,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lmgrid.h"
@@ -31,6 +33,9 @@ struct lmg_table {
     // stored at [(k * W + j) * 4 + s]. Degree 0 stores the node in c0.
     std::vector<float> coef32;
     std::vector<double> coef64;
+    // Correction vectors already computed, by grid size.
+    mutable std::mutex cache_mu;
+    mutable std::map<int, std::vector<double>> hpix_cache;
 };
 
 namespace lmg {

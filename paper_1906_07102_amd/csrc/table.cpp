@@ -465,6 +465,14 @@ lmg_status lmg_table_kernel(const lmg_table* t, int n, const double* delta, doub
 
 lmg_status lmg_correction(const lmg_table* t, int N, double* h_pix) {
     if (!t || !h_pix || N < 2 || (N & (N - 1))) return LMG_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(t->cache_mu);
+        auto it = t->hpix_cache.find(N);
+        if (it != t->hpix_cache.end()) {
+            std::memcpy(h_pix, it->second.data(), sizeof(double) * N);
+            return LMG_OK;
+        }
+    }
     std::vector<double> qd, qw;
     gauss_legendre(64, delta_low(t->W), delta_low(t->W) + 1.0, qd, qw);
     std::vector<double> kv(qd.size() * t->W);
@@ -477,6 +485,8 @@ lmg_status lmg_correction(const lmg_table* t, int N, double* h_pix) {
         if (p < N / 2) h_pix[N / 2 + p] = hv;
         h_pix[N / 2 - p] = hv;
     }
+    std::lock_guard<std::mutex> lk(t->cache_mu);
+    t->hpix_cache[N].assign(h_pix, h_pix + N);
     return LMG_OK;
 }
 
