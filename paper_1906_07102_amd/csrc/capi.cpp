@@ -33,11 +33,15 @@ struct lmg_plan {
     int cap = 0;
     int M = 0;                  // retained image size 2 x0 N
     bool bad_data = false;
+    // Occupied band of the grid (storage rows / columns [lo, hi)) and the
+    // window of tiles that covers it (first tile, number of tiles).
+    int band_r0 = 0, band_r1 = 0, band_c0 = 0, band_c1 = 0;
+    int win_r0 = 0, win_rn = 0, win_c0 = 0, win_cn = 0;
     int* flags = nullptr;
     int* tile_count = nullptr;
     int* tile_start = nullptr;
     int* item_start = nullptr;
-    int* cursor = nullptr;
+    int* blockhist = nullptr;      // per plan block and tile: counts, then offsets
     int4* items = nullptr;
     int* inv0 = nullptr;           // caller index -> tile-order position (-1: dropped)
     uint16_t* loc0 = nullptr;      // first-tap cell within the tile, by position
@@ -100,7 +104,7 @@ size_t cplx_size(lmg_precision p) { return 2 * real_size(p); }
 size_t patch_cell_size(lmg_precision p) { return p == LMG_F32 ? 8 : 16; }
 
 struct Layout {
-    size_t flags, tile_count, tile_start, item_start, cursor, items, inv0, loc0, dlt0, dlt, pos2, inv, pieces, coef,
+    size_t flags, tile_count, tile_start, item_start, blockhist, items, inv0, loc0, dlt0, dlt, pos2, inv, pieces, coef,
         twiddle, hpix, total;
     int max_items;
 };
@@ -117,7 +121,7 @@ Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap) {
     L.tile_count = take(ntiles * sizeof(int));
     L.tile_start = take((ntiles + 1) * sizeof(int));
     L.item_start = take((ntiles + 1) * sizeof(int));
-    L.cursor = take(ntiles * sizeof(int));
+    L.blockhist = take(static_cast<size_t>(plan_blocks(nvis)) * ntiles * sizeof(int));
     L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
     L.inv0 = take(static_cast<size_t>(nvis) * sizeof(int));
     L.loc0 = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
@@ -213,8 +217,37 @@ lmg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     return LMG_OK;
 }
 
+// Grid rows (or columns) touched by footprints of tiles lo..hi (inclusive),
+// as [r0, r1); the whole range if the footprints wrap around the grid edge.
+void axis_band(int lo, int hi, int T, int W, int N, int ntx, int* r0, int* r1, int* w0, int* wn) {
+    if (hi < lo) {                    // nothing gridded
+        *r0 = *r1 = 0;
+        *w0 = 0;
+        *wn = 0;
+        return;
+    }
+    const int end = (hi + 1) * T + W - 1;
+    if (end > N) {
+        *r0 = 0;
+        *r1 = N;
+        *w0 = 0;
+        *wn = ntx;
+        return;
+    }
+    *r0 = lo * T;
+    *r1 = end;
+    *w0 = lo;
+    *wn = std::min(hi + (W > 1 ? 1 : 0), ntx - 1) - lo + 1;
+}
+
+void set_band(lmg_plan* p, int rmin, int rmax, int cmin, int cmax) {
+    if (p->n_busy == 0) { rmax = -1; cmax = -1; rmin = 0; cmin = 0; }
+    axis_band(rmin, rmax, p->g.T, p->g.W, p->g.N, p->g.ntx, &p->band_r0, &p->band_r1, &p->win_r0, &p->win_rn);
+    axis_band(cmin, cmax, p->g.T, p->g.W, p->g.N, p->g.ntx, &p->band_c0, &p->band_c1, &p->win_c0, &p->win_cn);
+}
+
 lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
-                    hipStream_t s) {
+                    hipStream_t s, bool band_only = false) {
     const lmg_table* t = p->table;
     {
         TraceScope ts("permute_in", s);
@@ -231,6 +264,11 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     }
     AssembleArgs b{};
     b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx;
+    if (band_only) {                  // an internal grid: only the occupied window is ever read
+        b.tr0 = p->win_r0; b.trows = p->win_rn; b.tc0 = p->win_c0; b.tcols = p->win_cn;
+    } else {
+        b.tr0 = 0; b.trows = p->g.ntx; b.tc0 = 0; b.tcols = p->g.ntx;
+    }
     b.item_start = p->item_start; b.patches = patches; b.grid = grid;
     TraceScope ts("assemble", s);
     LMG_HIP(launch_assemble(p->prec, b, s));
@@ -312,7 +350,7 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
     p->tile_count = reinterpret_cast<int*>(base + L.tile_count);
     p->tile_start = reinterpret_cast<int*>(base + L.tile_start);
     p->item_start = reinterpret_cast<int*>(base + L.item_start);
-    p->cursor = reinterpret_cast<int*>(base + L.cursor);
+    p->blockhist = reinterpret_cast<int*>(base + L.blockhist);
     p->items = reinterpret_cast<int4*>(base + L.items);
     p->inv0 = reinterpret_cast<int*>(base + L.inv0);
     p->loc0 = reinterpret_cast<uint16_t*>(base + L.loc0);
@@ -340,19 +378,21 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
         LMG_HIP(hipStreamSynchronize(s));       // hf goes out of scope
     }
     LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
-    LMG_HIP(hipMemsetAsync(p->tile_count, 0, sizeof(int) * p->g.ntiles, s));
     {
         TraceScope ts("plan_count", s);
-        LMG_HIP(launch_plan_count(uv, nvis, p->g, p->tile_count, p->flags, s));
+        LMG_HIP(launch_plan_count(uv, nvis, p->g, p->blockhist, p->flags, s));
+    }
+    {
+        TraceScope ts("plan_colscan", s);
+        LMG_HIP(launch_plan_colscan(p->g, p->blockhist, plan_blocks(nvis), p->tile_count, s));
     }
     {
         TraceScope ts("plan_scan", s);
-        LMG_HIP(launch_plan_scan(p->g, p->tile_count, p->tile_start, p->item_start, p->cursor, p->items, p->flags,
-                                 cap, s));
+        LMG_HIP(launch_plan_scan(p->g, p->tile_count, p->tile_start, p->item_start, p->items, p->flags, cap, s));
     }
     {
         TraceScope ts("plan_scatter", s);
-        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->cursor, p->inv0, p->loc0,
+        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->blockhist, p->inv0, p->loc0,
                                     p->dlt0, s));
     }
     {
@@ -364,13 +404,14 @@ lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, in
         TraceScope ts("plan_compose", s);
         LMG_HIP(launch_plan_compose(p->inv0, p->pos2, nvis, p->inv, s));
     }
-    int flags[4] = {0, 0, 0, 0};
+    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
     LMG_HIP(hipStreamSynchronize(s));
     p->bad_data = flags[0] != 0;
     p->n_items = flags[1];
     p->n_valid = flags[2];
     p->n_busy = flags[3];
+    set_band(p.get(), flags[4], flags[5], flags[6], flags[7]);
     if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
     *out = p.release();
     return LMG_OK;
@@ -427,20 +468,31 @@ lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, cons
     char* sc = static_cast<char*>(scratch);
     void* grid = sc + L.grid;
     void* tmp = sc + L.tmp;
-    lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, s);
+    lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, s, true);
     if (st != LMG_OK) return st;
     const bool f64 = p->prec == LMG_F64;
-    // Rows m of the grid: transform over n, keep the central M outputs, write transposed (tmp is M x N).
+    const size_t cs = cplx_size(p->prec);
+    const int r0 = p->band_r0, nr = p->band_r1 - p->band_r0, c0 = p->band_c0, nc = p->band_c1 - p->band_c0;
+    if (nr == 0) {                     // nothing gridded: the image is zero
+        LMG_HIP(hipMemsetAsync(image, 0, static_cast<size_t>(M) * M * cs, s));
+        return LMG_OK;
+    }
+    // Rows m of the occupied band: transform over n (only the occupied columns are non-zero), keep the
+    // central M outputs, write transposed (tmp is M x N; only columns r0 .. r0 + nr are written).
     FftArgs a = fft_args(N, +1, p->twiddle);
-    a.nrows = N; a.src = grid; a.src_pitch = N; a.in_count = N; a.in_pos = 0;
-    a.dst = tmp; a.dst_pitch = N; a.out_count = M; a.out_pos = N / 2 - M / 2;
+    a.nrows = nr; a.src = static_cast<char*>(grid) + (static_cast<size_t>(r0) * N + c0) * cs; a.src_pitch = N;
+    a.in_count = nc; a.in_pos = c0;
+    a.dst = static_cast<char*>(tmp) + static_cast<size_t>(r0) * cs; a.dst_pitch = N; a.out_count = M;
+    a.out_pos = N / 2 - M / 2;
     {
         TraceScope ts("fft_rows_inverse", s);
         LMG_HIP(launch_fft_pass(f64, a, s));
     }
-    // Rows p of tmp: transform over m, keep the central M outputs, apply h(x_p) h(y_q), write image[q][p].
+    // Rows p of tmp: transform over m (zero outside the band), keep the central M outputs, apply
+    // h(x_p) h(y_q), write image[q][p].
     FftArgs b = fft_args(N, +1, p->twiddle);
-    b.nrows = M; b.src = tmp; b.src_pitch = N; b.in_count = N; b.in_pos = 0;
+    b.nrows = M; b.src = static_cast<char*>(tmp) + static_cast<size_t>(r0) * cs; b.src_pitch = N;
+    b.in_count = nr; b.in_pos = r0;
     b.dst = image; b.dst_pitch = M; b.out_count = M; b.out_pos = N / 2 - M / 2;
     b.h_out = p->hpix; b.h_row = p->hpix; b.row_off = N / 2 - M / 2;
     TraceScope ts("fft_cols_inverse_correct_crop", s);
@@ -459,22 +511,28 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
     void* grid = sc + L.grid;
     void* tmp = sc + L.tmp;
     const bool f64 = p->prec == LMG_F64;
-    // Rows q of the image: correct by h(x_p) h(y_q), zero-pad to N, transform over p, write transposed (tmp N x M).
-    FftArgs a = fft_args(N, -1, p->twiddle);
-    a.nrows = M; a.src = image; a.src_pitch = M; a.in_count = M; a.in_pos = N / 2 - M / 2;
-    a.dst = tmp; a.dst_pitch = M; a.out_count = N; a.out_pos = 0;
-    a.h_in = p->hpix; a.h_row = p->hpix; a.row_off = N / 2 - M / 2;
-    {
-        TraceScope ts("fft_rows_forward_correct_pad", s);
-        LMG_HIP(launch_fft_pass(f64, a, s));
-    }
-    // Rows n of tmp: zero-pad to N, transform over q, write grid[m][n].
-    FftArgs b = fft_args(N, -1, p->twiddle);
-    b.nrows = N; b.src = tmp; b.src_pitch = M; b.in_count = M; b.in_pos = N / 2 - M / 2;
-    b.dst = grid; b.dst_pitch = N; b.out_count = N; b.out_pos = 0;
-    {
-        TraceScope ts("fft_cols_forward", s);
-        LMG_HIP(launch_fft_pass(f64, b, s));
+    const size_t cs = cplx_size(p->prec);
+    const int r0 = p->band_r0, nr = p->band_r1 - p->band_r0, c0 = p->band_c0, nc = p->band_c1 - p->band_c0;
+    if (nr > 0) {
+        // Rows q of the image: correct by h(x_p) h(y_q), zero-pad to N, transform over p, keep the outputs n in
+        // the occupied column band, write transposed (tmp: nc rows n, M columns q).
+        FftArgs a = fft_args(N, -1, p->twiddle);
+        a.nrows = M; a.src = image; a.src_pitch = M; a.in_count = M; a.in_pos = N / 2 - M / 2;
+        a.dst = tmp; a.dst_pitch = M; a.out_count = nc; a.out_pos = c0;
+        a.h_in = p->hpix; a.h_row = p->hpix; a.row_off = N / 2 - M / 2;
+        {
+            TraceScope ts("fft_rows_forward_correct_pad", s);
+            LMG_HIP(launch_fft_pass(f64, a, s));
+        }
+        // Rows n of tmp: zero-pad to N, transform over q, write the occupied band of grid rows m.
+        FftArgs b = fft_args(N, -1, p->twiddle);
+        b.nrows = nc; b.src = tmp; b.src_pitch = M; b.in_count = M; b.in_pos = N / 2 - M / 2;
+        b.dst = static_cast<char*>(grid) + (static_cast<size_t>(r0) * N + c0) * cs; b.dst_pitch = N;
+        b.out_count = nr; b.out_pos = r0;
+        {
+            TraceScope ts("fft_cols_forward", s);
+            LMG_HIP(launch_fft_pass(f64, b, s));
+        }
     }
     return run_degrid(p, grid, vis_out, sc + L.vs, s);
 }

@@ -9,8 +9,11 @@
 
 namespace lmg {
 
-// Visibilities handled by one block of the plan kernels.
-constexpr int kPlanChunk = 4096;
+// The plan's streaming passes over the visibilities: blocks of kPlanThreads
+// threads, each handling kPlanBlockVis consecutive visibilities.
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanBlockVis = 65536;
+inline int plan_blocks(int64_t nvis) { return static_cast<int>((nvis + kPlanBlockVis - 1) / kPlanBlockVis); }
 // Longest run of one footprint cell handled by one lane (a "piece").
 constexpr int kPiece = 32;
 // Largest work item (visibilities); bounded by the 16-bit in-item offsets.
@@ -38,6 +41,7 @@ struct GridArgs {
 
 struct AssembleArgs {
     int N, W, T, ntx;
+    int tr0, tc0, trows, tcols;   // window of tiles written (rows tr0.., columns tc0.., wrapping)
     const int* item_start;   // per tile, ntiles + 1
     const void* patches;
     void* grid;
@@ -71,12 +75,13 @@ struct FftArgs {
     int row_off;
 };
 
-hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* tile_count, int* flags,
+hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* blockhist, int* flags,
                              hipStream_t s);
-hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int* cursor,
-                            int4* items, int* flags, int cap, hipStream_t s);
+hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, int nb, int* tile_count, hipStream_t s);
+hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
+                            int* flags, int cap, hipStream_t s);
 hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               int* cursor, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s);
+                               const int* blockhist, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s);
 hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
                             const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
                             hipStream_t s);

@@ -68,39 +68,75 @@ __device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int d
 
 __device__ __forceinline__ int cell_of(int loc, int T) { return (loc >> 8) * T + (loc & 255); }
 
+// Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+// Streaming kernels map workgroup b to chunk xcd_chunk(b, nb), so that every
+// XCD walks one contiguous run of chunks and data written or read by
+// neighbouring chunks (e.g. successive times of one baseline) meet in the
+// same L2.
+__device__ __forceinline__ int xcd_chunk(int b, int nb) {
+    const int x = b & 7, i = b >> 3;
+    const int q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + i;
+}
+
 // ---------------------------------------------------------------- plan
-// Pass 1: validate coordinates and count visibilities per tile.
-__global__ __launch_bounds__(256) void k_plan_count(const double2* __restrict__ uv, int64_t nvis, PlanGeom g,
-                                                    int* __restrict__ tile_count, int* __restrict__ flags) {
+// Pass 1: validate coordinates and count visibilities per tile, per block of
+// kPlanBlockVis visibilities (kept per block, so that pass 3 can place each
+// block's visibilities of a tile in one contiguous run).
+__global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __restrict__ uv, int64_t nvis, PlanGeom g,
+                                                             int* __restrict__ blockhist, int nb,
+                                                             int* __restrict__ flags) {
     extern __shared__ int hist[];
     for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) hist[t] = 0;
     __syncthreads();
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+    const int chunk = xcd_chunk(blockIdx.x, nb);
+    const int64_t base = static_cast<int64_t>(chunk) * kPlanBlockVis;
     int bad = 0;
-    for (int i = threadIdx.x; i < kPlanChunk; i += blockDim.x) {
-        const int64_t k = base + i;
-        if (k >= nvis) break;
-        const double2 c = uv[k];
-        int cu, cv;
-        double du, dv;
-        if (tap_geometry(c.x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c.y, g.W, g.ref, g.N, &cv, &dv)) {
-            const int t = (cv / g.T) * g.ntx + (cu / g.T);
-            atomicAdd(&hist[t], 1);
-        } else {
-            bad = 1;
+    constexpr int kB = 8;
+    for (int i0 = 0; i0 < kPlanBlockVis; i0 += kB * kPlanThreads) {
+        double2 c[kB];
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
+            if (k < nvis) c[u] = uv[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
+            if (k >= nvis) break;
+            int cu, cv;
+            double du, dv;
+            if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv))
+                atomicAdd(&hist[(cv / g.T) * g.ntx + (cu / g.T)], 1);
+            else
+                bad = 1;
         }
     }
     if (bad) atomicOr(&flags[0], 1);
     __syncthreads();
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x)
-        if (hist[t]) atomicAdd(&tile_count[t], hist[t]);
+    int* row = blockhist + static_cast<size_t>(chunk) * g.ntiles;
+    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) row[t] = hist[t];
+}
+
+// Pass 1b: per tile, the exclusive prefix of the block counts (in place) and the total.
+__global__ __launch_bounds__(256) void k_plan_colscan(PlanGeom g, int* __restrict__ blockhist, int nb,
+                                                      int* __restrict__ tile_count) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= g.ntiles) return;
+    int run = 0;
+    for (int c = 0; c < nb; ++c) {
+        int* p = blockhist + static_cast<size_t>(c) * g.ntiles + t;
+        const int x = *p;
+        *p = run;
+        run += x;
+    }
+    tile_count[t] = run;
 }
 
 // Pass 2 (one workgroup): tile offsets, work items, cursors.
 __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __restrict__ tile_count,
                                                     int* __restrict__ tile_start, int* __restrict__ item_start,
-                                                    int* __restrict__ tile_cursor, int4* __restrict__ items,
-                                                    int* __restrict__ flags, int cap) {
+                                                    int4* __restrict__ items, int* __restrict__ flags, int cap) {
     __shared__ int part[1024];
     __shared__ int part2[1024];
     const int nt = g.ntiles;
@@ -132,12 +168,18 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
     s = part[threadIdx.x];
     si = part2[threadIdx.x];
     int busy = 0;
+    int rmin = 1 << 30, rmax = -1, cmin = 1 << 30, cmax = -1;   // occupied tile rows and columns
     for (int t = lo; t < hi; ++t) {
         const int c = tile_count[t];
         const int ni = (c + cap - 1) / cap;
         tile_start[t] = s;
         item_start[t] = si;
-        tile_cursor[t] = 0;
+        if (c > 0) {
+            rmin = min(rmin, t / g.ntx);
+            rmax = max(rmax, t / g.ntx);
+            cmin = min(cmin, t % g.ntx);
+            cmax = max(cmax, t % g.ntx);
+        }
         for (int q = 0; q < ni; ++q) {
             const int a = static_cast<int>((static_cast<int64_t>(c) * q) / ni);
             const int b = static_cast<int>((static_cast<int64_t>(c) * (q + 1)) / ni);
@@ -147,60 +189,76 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
         s += c;
         si += ni;
     }
-    if (busy) atomicAdd(&flags[3], busy);
+    __syncthreads();
+    part[threadIdx.x] = busy;
+    part2[threadIdx.x] = rmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0, m = 1 << 30;
+        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) { b += part[i]; m = min(m, part2[i]); }
+        flags[3] = b;
+        flags[4] = m;
+    }
+    __syncthreads();
+    part[threadIdx.x] = rmax;
+    part2[threadIdx.x] = cmin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = -1, m = 1 << 30;
+        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) { a = max(a, part[i]); m = min(m, part2[i]); }
+        flags[5] = a;
+        flags[6] = m;
+    }
+    __syncthreads();
+    part[threadIdx.x] = cmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = -1;
+        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) a = max(a, part[i]);
+        flags[7] = a;
+    }
 }
 
 // Pass 3: give each visibility its tile-order position; store its local
 // first-tap cell and offsets there, and the position under its caller index.
 template <typename R>
-__global__ __launch_bounds__(256) void k_plan_scatter(const double2* __restrict__ uv, int64_t nvis, PlanGeom g,
-                                                      const int* __restrict__ tile_start, int* __restrict__ tile_cursor,
-                                                      int* __restrict__ inv, uint16_t* __restrict__ loc0,
-                                                      typename C2<R>::T* __restrict__ dlt0) {
-    extern __shared__ int hist[];
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) hist[t] = 0;
+__global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __restrict__ uv, int64_t nvis,
+                                                               PlanGeom g, const int* __restrict__ tile_start,
+                                                               const int* __restrict__ blockhist, int nb,
+                                                               int* __restrict__ inv, uint16_t* __restrict__ loc0,
+                                                               typename C2<R>::T* __restrict__ dlt0) {
+    extern __shared__ int cur[];
+    const int chunk = xcd_chunk(blockIdx.x, nb);
+    const int* row = blockhist + static_cast<size_t>(chunk) * g.ntiles;
+    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) cur[t] = tile_start[t] + row[t];
     __syncthreads();
-    constexpr int kPer = kPlanChunk / 256;
-    int tile[kPer], rank[kPer];
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * kPlanChunk;
+    const int64_t base = static_cast<int64_t>(chunk) * kPlanBlockVis;
+    constexpr int kB = 8;                                    // coordinates loaded together per thread
+    for (int i0 = 0; i0 < kPlanBlockVis; i0 += kB * kPlanThreads) {
+        double2 c[kB];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        const int64_t k = base + q * 256 + threadIdx.x;
-        tile[q] = -1;
-        if (k < nvis) {
-            const double2 c = uv[k];
+        for (int u = 0; u < kB; ++u) {
+            const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
+            if (k < nvis) c[u] = uv[k];
+        }
+#pragma unroll
+        for (int u = 0; u < kB; ++u) {
+            const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
+            if (k >= nvis) break;
             int cu, cv;
             double du, dv;
-            if (tap_geometry(c.x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c.y, g.W, g.ref, g.N, &cv, &dv)) {
-                tile[q] = (cv / g.T) * g.ntx + (cu / g.T);
-                rank[q] = atomicAdd(&hist[tile[q]], 1);
+            if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv)) {
+                const int dst = atomicAdd(&cur[(cv / g.T) * g.ntx + (cu / g.T)], 1);
+                inv[k] = dst;
+                loc0[dst] = static_cast<uint16_t>(((cv % g.T) << 8) | (cu % g.T));
+                typename C2<R>::T d;
+                d.x = static_cast<R>(du);
+                d.y = static_cast<R>(dv);
+                dlt0[dst] = d;
             } else {
                 inv[k] = -1;                       // dropped: no position
             }
         }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) {
-        const int c = hist[t];
-        if (c) hist[t] = tile_start[t] + atomicAdd(&tile_cursor[t], c);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-        if (tile[q] < 0) continue;
-        const int64_t k = base + q * 256 + threadIdx.x;
-        const double2 c = uv[k];
-        int cu, cv;
-        double du, dv;
-        tap_geometry(c.x, g.W, g.ref, g.N, &cu, &du);
-        tap_geometry(c.y, g.W, g.ref, g.N, &cv, &dv);
-        const int dst = hist[tile[q]] + rank[q];
-        inv[k] = dst;
-        loc0[dst] = static_cast<uint16_t>(((cv % g.T) << 8) | (cu % g.T));
-        typename C2<R>::T d;
-        d.x = static_cast<R>(du);
-        d.y = static_cast<R>(dv);
-        dlt0[dst] = d;
     }
 }
 
@@ -291,7 +349,7 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
 // permutations need a single lookup: inv[k] = pos2[inv0[k]].
 __global__ __launch_bounds__(256) void k_plan_compose(const int* __restrict__ inv0, const int* __restrict__ pos2,
                                                       int64_t nvis, int* __restrict__ inv) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
     const int p = inv0[k];
     inv[k] = p < 0 ? -1 : pos2[p];
@@ -303,7 +361,7 @@ template <typename R>
 __global__ __launch_bounds__(256) void k_permute_in(const typename C2<R>::T* __restrict__ vis, const float* __restrict__ w,
                                                     const int* __restrict__ inv, int64_t nvis,
                                                     typename C2<R>::T* __restrict__ vs) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
     const int d = inv[k];
     if (d < 0) return;
@@ -320,7 +378,7 @@ __global__ __launch_bounds__(256) void k_permute_in(const typename C2<R>::T* __r
 template <typename R>
 __global__ __launch_bounds__(256) void k_permute_out(const typename C2<R>::T* __restrict__ vs, const int* __restrict__ inv,
                                                      int64_t nvis, typename C2<R>::T* __restrict__ out) {
-    const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
     const int d = inv[k];
     typename C2<R>::T v;
@@ -500,7 +558,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     for (int i = threadIdx.x; i < kGridWaves * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
     __syncthreads();
-    const int4 it = a.items[blockIdx.x];
+    const int item = xcd_chunk(blockIdx.x, gridDim.x);
+    const int4 it = a.items[item];
     const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
     const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
     const R dlo = static_cast<R>(a.dlo);
@@ -558,7 +617,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
         if constexpr (kRegs) flush_piece<Acc, W>(patch, owner, P, lane, have && len > 0, l, acc);
     }
     __syncthreads();
-    Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(blockIdx.x) * P2;
+    Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(item) * P2;
     for (int i = threadIdx.x; i < P2; i += blockDim.x) {
         double re = 0.0, im = 0.0;
 #pragma unroll
@@ -577,9 +636,10 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
     const int nblk = a.T / kAssembleRows;
-    const int t = blockIdx.x / nblk;
+    const int wt = blockIdx.x / nblk;                       // tile within the written window
     const int rb = (blockIdx.x % nblk) * kAssembleRows;
-    const int tm = t / a.ntx, tn = t % a.ntx;
+    const int tm = (a.tr0 + wt / a.tcols) % a.ntx, tn = (a.tc0 + wt % a.tcols) % a.ntx;
+    const int t = tm * a.ntx + tn;
     const int P = a.T + a.W - 1;
     const int halo = a.W - 1;
     const Cell* patches = reinterpret_cast<const Cell*>(a.patches);
@@ -629,7 +689,7 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     const int P = a.T + W - 1;
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
-    const int4 it = a.items[blockIdx.x];
+    const int4 it = a.items[xcd_chunk(blockIdx.x, gridDim.x)];
     const int tm = it.x / a.ntx, tn = it.x % a.ntx;
     const VT* grid = reinterpret_cast<const VT*>(a.grid);
     for (int i = threadIdx.x; i < P * P; i += blockDim.x) {
@@ -882,34 +942,39 @@ hipError_t dispatch_degrid(const DegridArgs& a, hipStream_t s) {
 }
 }  // namespace
 
-hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* tile_count, int* flags,
+hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* blockhist, int* flags,
                              hipStream_t s) {
-    const int64_t nb = (nvis + kPlanChunk - 1) / kPlanChunk;
+    const int nb = plan_blocks(nvis);
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::k_plan_count, dim3(static_cast<unsigned>(nb)), dim3(256), g.ntiles * sizeof(int), s,
-                       reinterpret_cast<const double2*>(uv), nvis, g, tile_count, flags);
+    hipLaunchKernelGGL(dev::k_plan_count, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
+                       reinterpret_cast<const double2*>(uv), nvis, g, blockhist, nb, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int* cursor,
-                            int4* items, int* flags, int cap, hipStream_t s) {
-    hipLaunchKernelGGL(dev::k_plan_scan, dim3(1), dim3(1024), 0, s, g, tile_count, tile_start, item_start, cursor,
-                       items, flags, cap);
+hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, int nb, int* tile_count, hipStream_t s) {
+    hipLaunchKernelGGL(dev::k_plan_colscan, dim3((g.ntiles + 255) / 256), dim3(256), 0, s, g, blockhist, nb, tile_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
+                            int* flags, int cap, hipStream_t s) {
+    hipLaunchKernelGGL(dev::k_plan_scan, dim3(1), dim3(1024), 0, s, g, tile_count, tile_start, item_start, items,
+                       flags, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               int* cursor, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s) {
-    const int64_t nb = (nvis + kPlanChunk - 1) / kPlanChunk;
+                               const int* blockhist, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s) {
+    const int nb = plan_blocks(nvis);
     if (nb == 0) return hipSuccess;
     if (f64)
-        hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(static_cast<unsigned>(nb)), dim3(256),
-                           g.ntiles * sizeof(int), s, reinterpret_cast<const double2*>(uv), nvis, g, tile_start,
-                           cursor, inv, loc0, reinterpret_cast<double2*>(dlt0));
+        hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
+                           reinterpret_cast<const double2*>(uv), nvis, g, tile_start, blockhist, nb, inv, loc0,
+                           reinterpret_cast<double2*>(dlt0));
     else
-        hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(static_cast<unsigned>(nb)), dim3(256),
-                           g.ntiles * sizeof(int), s, reinterpret_cast<const double2*>(uv), nvis, g, tile_start,
-                           cursor, inv, loc0, reinterpret_cast<float2*>(dlt0));
+        hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
+                           reinterpret_cast<const double2*>(uv), nvis, g, tile_start, blockhist, nb, inv, loc0,
+                           reinterpret_cast<float2*>(dlt0));
     return hipGetLastError();
 }
 
@@ -970,7 +1035,8 @@ hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s) {
-    const unsigned nt = static_cast<unsigned>(a.ntx * a.ntx * (a.T / dev::kAssembleRows));
+    const unsigned nt = static_cast<unsigned>(a.trows * a.tcols * (a.T / dev::kAssembleRows));
+    if (nt == 0) return hipSuccess;
     switch (prec) {
         case LMG_F32: hipLaunchKernelGGL((dev::k_assemble<float, dev::AccF32>), dim3(nt), dim3(256), 0, s, a); break;
         case LMG_F32_KAHAN:
