@@ -75,6 +75,91 @@ def load_traffic(kernel: str, nvis: int):
     return None if k is None else k.get("bytes_per_launch")
 
 
+# Library trace names -> device kernel symbols (rocprofv3 names them by symbol).
+TRACE_TO_SYMBOL = {
+    "plan_count": "k_plan_count", "plan_colscan": "k_plan_colscan", "plan_scan": "k_plan_scan",
+    "plan_scatter": "k_plan_scatter", "plan_sort_items": "k_plan_sort_items", "plan_compose": "k_plan_compose",
+    "permute_in": "k_permute_in", "grid_items": "k_grid_items", "assemble": "k_assemble",
+    "degrid_items": "k_degrid_items", "permute_out": "k_permute_out",
+}
+CALIBRATION_SYMBOL = "MulFunctor"       # torch.mul(a, 1.0, out=b) over 2^28 floats: 1 GiB read + 1 GiB written
+CALIBRATION_BYTES = float(1 << 30)
+
+
+def _short_name(kernel_name: str) -> str:
+    import re
+    k = re.sub(r"\(.*", "", kernel_name)
+    return k.replace("void lmg::dev::", "").replace("lmg::dev::", "").strip()
+
+
+def summarize_trace(stats_csv: str, command: str) -> str:
+    """Text summary of a rocprofv3 --kernel-trace --stats kernel_stats.csv."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"# rocprofv3 kernel statistics", f"# command: {command}", "",
+           f"{'kernel':58s} {'calls':>6s} {'avg_us':>10s} {'min_us':>10s} {'max_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        out.append(f"{_short_name(r['Name'])[:58]:58s} {int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:10.2f} "
+                   f"{float(r['MinNs']) / 1e3:10.2f} {float(r['MaxNs']) / 1e3:10.2f} "
+                   f"{float(r['TotalDurationNs']) / 1e6:10.3f} {100 * float(r['TotalDurationNs']) / tot:6.2f}")
+    return "\n".join(out) + "\n"
+
+
+def _counter_per_dispatch(path: str, counter: str):
+    """{short kernel name: [value per dispatch, ...]} for one counter of a --pmc counter_collection.csv."""
+    import csv
+    import collections
+    per = collections.defaultdict(float)
+    names = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        per[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        names[r["Dispatch_Id"]] = r["Kernel_Name"]
+    out = collections.defaultdict(list)
+    for d, v in per.items():
+        out[_short_name(names[d])].append(v)
+    return out
+
+
+def summarize_traffic(fetch_csv: str, write_csv: str, command: str, nvis: int):
+    """HBM bytes per launch from FETCH_SIZE and WRITE_SIZE passes (KiB per dispatch), each scaled by what the
+    same counter reads for a plain 1 GiB copy in the same run. Returns (text, json dict)."""
+    fetch = _counter_per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_csv, "WRITE_SIZE")
+
+    def calib(d):
+        vals = [v for k, vs in d.items() if CALIBRATION_SYMBOL in k for v in vs if v * 1024 > CALIBRATION_BYTES / 2]
+        if not vals:
+            raise SystemExit("calibration copy not found in the counter run (bench.py --copy-calibration)")
+        return CALIBRATION_BYTES / (float(np.median(vals)) * 1024.0)
+    fr, wr = calib(fetch), calib(write)
+    kernels = {}
+    lines = [f"# HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch)",
+             f"# command (FETCH_SIZE pass): {command.replace('PMC', 'FETCH_SIZE')}",
+             f"# command (WRITE_SIZE pass): {command.replace('PMC', 'WRITE_SIZE')}",
+             f"# calibration: torch.mul(a, 1.0, out=b) over 1 GiB; bytes = counter KiB x 1024 x factor; "
+             f"fetch factor {fr:.4f}, write factor {wr:.4f}",
+             f"# nvis {nvis}", "",
+             f"{'trace name':24s} {'kernel':44s} {'launches':>8s} {'fetch_MB':>10s} {'write_MB':>10s} {'B/vis':>8s}"]
+    for trace, sym in TRACE_TO_SYMBOL.items():
+        f = [v for k, vs in fetch.items() if k.startswith(sym + "<") or k == sym for v in vs]
+        w = [v for k, vs in write.items() if k.startswith(sym + "<") or k == sym for v in vs]
+        if not f or not w:
+            continue
+        fb = float(np.median(f)) * 1024.0 * fr
+        wb = float(np.median(w)) * 1024.0 * wr
+        kname = next(k for k in fetch if k.startswith(sym))
+        kernels[trace] = {"kernel": kname, "fetch_bytes": round(fb), "write_bytes": round(wb),
+                          "bytes_per_launch": round(fb + wb)}
+        lines.append(f"{trace:24s} {kname[:44]:44s} {len(f):8d} {fb / 1e6:10.2f} {wb / 1e6:10.2f} "
+                     f"{(fb + wb) / nvis:8.2f}")
+    data = {"source_hash": kernel_source_hash(), "nvis": nvis, "fetch_factor": fr, "write_factor": wr,
+            "kernels": kernels}
+    return "\n".join(lines) + "\n", data
+
+
 def cpu_baseline(case, nvis_sample: int):
     """The FP64 oracle on a bounded sample of the same workload, scaled to visibilities/s of a whole step."""
     from oracle import imaging as im
@@ -117,7 +202,22 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="print a text summary of a rocprofv3 --stats run and exit (no GPU use)")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from FETCH_SIZE and WRITE_SIZE passes, print a summary, exit")
+    ap.add_argument("--profile-command", default="", help="command line recorded in a summary")
+    ap.add_argument("--nvis", type=int, default=16777152, help="visibilities of the profiled run (traffic summary)")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.profile_command), end="")
+        return
+    if args.summarize_traffic:
+        text, data = summarize_traffic(*args.summarize_traffic, args.profile_command, args.nvis)
+        with open(os.path.join(HERE, "profiles", "traffic.json"), "w") as f:
+            json.dump(data, f, indent=1)
+        print(text, end="")
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
               f"(multi-GPU sharding is a design note only)", file=sys.stderr)
@@ -188,7 +288,8 @@ def main():
         avg = tot / n
         ab = algorithmic_bytes(name, nvis, N, M, cs)
         kernels[name] = {"launches": n, "avg_ms": round(avg, 5),
-                         "algorithmic_GBps": round(ab / (avg * 1e-3) / 1e9, 1) if ab else None}
+                         "algorithmic_GBps": round(ab / (avg * 1e-3) / 1e9, 1) if ab else None,
+                         "traffic": load_traffic(name, nvis)}
     dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
     dom_avg_s = trace[dom][1] / trace[dom][0] * 1e-3
     ab = algorithmic_bytes(dom, nvis, N, M, cs)
@@ -196,11 +297,12 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, nvis), "kernel": dom}
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
+        del a, b
 
     out = {
         "metric": METRIC,
