@@ -47,7 +47,7 @@ typedef enum {
 } lmg_status;
 
 typedef enum {
-    LMG_F32 = 0,        /* complex64 data, FP32 accumulation with LDS atomics */
+    LMG_F32 = 0,        /* complex64 data, plain FP32 accumulation */
     LMG_F32_KAHAN = 1,  /* complex64 data, compensated (two-float) FP32 accumulation */
     LMG_F64 = 2         /* complex128 data, FP64 throughout */
 } lmg_precision;
@@ -127,7 +127,7 @@ void lmg_table_destroy(lmg_table* t);
  * Sec. 6.2). The plan keeps pointers into `workspace` and a reference to
  * `table`: both must outlive it.
  *
- * N: power of two in [max(64, 2W), 16384]; x0 * N * 2 an integer (taken
+ * N: power of two in [max(64, 2W), 8192]; x0 * N * 2 an integer (taken
  * from the table). nvis >= 0. uv: device (nvis, 2) float64.
  * lmg_plan_create synchronizes `stream` once, to size the work lists; it
  * leaves LMG_EDATA to be reported by lmg_plan_check when a coordinate is NaN
