@@ -193,6 +193,40 @@ lmg_status lmg_make_dirty_image(const lmg_table* t, int N, lmg_precision prec, i
 lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
                                     const void* image, void* vis_out, void* workspace, size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------- batched channels
+ * Many independent problems (e.g. frequency channels) with uneven numbers of
+ * visibilities, each gridded onto its own N x N grid, in one plan and one
+ * launch per kernel (not part of the paper's method, which images one
+ * channel; the per-channel arithmetic is that of lmg_grid / lmg_degrid).
+ * Channel c owns the visibilities [offsets[c], offsets[c+1]) of uv / vis and
+ * grid c of `grids` (nchan x N x N, device, channel-major). offsets: host,
+ * nchan + 1 non-decreasing int64 with offsets[0] = 0. nchan in [1, 65536].
+ * The plan is an lmg_plan: lmg_grid_planned and lmg_degrid_planned accept it
+ * and then read / write nchan grids; lmg_make_dirty_image_planned and
+ * lmg_predict_visibilities_planned return LMG_ENOTSUP for nchan > 1.
+ * tile: edge of the uv tiles in cells, 0 for the library default, else a
+ * power of two in [8, min(128, N)] with N / tile <= 128 (LMG_EINVAL
+ * otherwise); the best value depends on the density of the data, which is
+ * what an autotuner measures. Workspace sizes are upper bounds for any tile.
+ */
+lmg_status lmg_batch_workspace_size(int N, int W, int nchan, int64_t nvis, lmg_precision prec, size_t* bytes);
+lmg_status lmg_batch_plan_create(const lmg_table* table, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                                 const double* uv, int tile, void* workspace, size_t ws_bytes, void* stream,
+                                 lmg_plan** out);
+/* Channels, tile edge and waves per gridding workgroup of a plan (any pointer may be NULL). */
+lmg_status lmg_batch_info(const lmg_plan* p, int* nchan, int* tile, int* waves);
+
+/* One-shot batched gridding (overwrites all nchan grids) and degridding; op is
+ * LMG_OP_GRID or LMG_OP_DEGRID. These synchronize `stream` once. */
+lmg_status lmg_workspace_size_batched(int N, int W, int nchan, int64_t nvis, lmg_precision prec, int op,
+                                      size_t* bytes);
+lmg_status lmg_grid_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                            const double* uv, const void* vis, const float* w, void* grids, void* ws,
+                            size_t ws_bytes, void* stream);
+lmg_status lmg_degrid_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                              const double* uv, const void* grids, void* vis_out, void* ws, size_t ws_bytes,
+                              void* stream);
+
 /* ------------------------------------------------------- 2D FFT building block
  * Centred 2D transform F[q][p] = sum_{m,n} G[m][n] exp(sign i 2 pi (n p + m q) / N)
  * of an N x N device array in place of `data` (all indices centred in

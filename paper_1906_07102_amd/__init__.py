@@ -18,8 +18,10 @@ from typing import Optional
 import numpy as np
 
 __all__ = [
-    "F32", "F32_KAHAN", "F64", "LmgError", "LibraryMissing", "Table", "Plan", "library_path", "load",
-    "grid", "degrid", "make_dirty_image", "predict_visibilities", "fft2_centred", "trace_enable", "trace_report",
+    "F32", "F32_KAHAN", "F64", "LmgError", "LibraryMissing", "Table", "Plan", "BatchPlan", "autotune_batch",
+    "library_path", "load", "grid", "degrid", "make_dirty_image", "predict_visibilities", "grid_batched",
+    "degrid_batched", "fft2_centred", "trace_enable", "trace_report", "Degrid", "Grid", "PredictVisibilities",
+    "MakeDirtyImage",
 ]
 
 F32, F32_KAHAN, F64 = 0, 1, 2
@@ -93,6 +95,12 @@ def load():
         "lmg_make_dirty_image": (I, [P, I, I, I64, P, P, P, P, P, Z, P]),
         "lmg_predict_visibilities": (I, [P, I, I, I64, P, P, P, P, Z, P]),
         "lmg_fft2_centred": (I, [I, I, I, P, P, P]),
+        "lmg_batch_workspace_size": (I, [I, I, I, I64, I, PZ]),
+        "lmg_batch_plan_create": (I, [P, I, I, I, ctypes.POINTER(I64), P, I, P, Z, P, ctypes.POINTER(P)]),
+        "lmg_batch_info": (I, [P, PI, PI, PI]),
+        "lmg_workspace_size_batched": (I, [I, I, I, I64, I, I, PZ]),
+        "lmg_grid_batched": (I, [P, I, I, I, ctypes.POINTER(I64), P, P, P, P, P, Z, P]),
+        "lmg_degrid_batched": (I, [P, I, I, I, ctypes.POINTER(I64), P, P, P, P, Z, P]),
         "lmg_trace_enable": (I, [I]),
         "lmg_trace_report": (I, [ctypes.c_char_p, Z]),
         "lmg_status_string": (ctypes.c_char_p, [I]),
@@ -273,6 +281,11 @@ class Plan:
                    "lmg_plan_create")
         self._h = h
         self._scratch = {}
+        self.nchan = 1
+
+    @property
+    def grid_shape(self):
+        return (self.N, self.N) if self.nchan == 1 else (self.nchan, self.N, self.N)
 
     @property
     def handle(self):
@@ -303,8 +316,8 @@ class Plan:
         if weights is not None:
             _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
         if out is None:
-            out = torch.empty((self.N, self.N), dtype=self._vis_dtype(), device=self.device)
-        _check_tensor(out, "grid", self._vis_dtype(), (self.N, self.N), self.device)
+            out = torch.empty(self.grid_shape, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "grid", self._vis_dtype(), self.grid_shape, self.device)
         sc = self.scratch(OP_GRID)
         _check(self.lib.lmg_grid_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), _ptr(sc), sc.numel(),
                                          _stream_handle(stream)), "lmg_grid_planned")
@@ -312,7 +325,7 @@ class Plan:
 
     def degrid(self, grid, out=None, stream=None):
         torch = _torch()
-        _check_tensor(grid, "grid", self._vis_dtype(), (self.N, self.N), self.device)
+        _check_tensor(grid, "grid", self._vis_dtype(), self.grid_shape, self.device)
         if out is None:
             out = torch.empty(self.nvis, dtype=self._vis_dtype(), device=self.device)
         _check_tensor(out, "vis_out", self._vis_dtype(), (self.nvis,), self.device)
@@ -354,6 +367,252 @@ class Plan:
                 self._h = None
         except Exception:
             pass
+
+
+# ------------------------------------------------------------ batched channels
+def _offsets_array(offsets) -> np.ndarray:
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    if off.ndim != 1 or len(off) < 2:
+        raise ValueError("offsets must be a 1-D sequence of nchan + 1 integers")
+    return off
+
+
+class BatchPlan(Plan):
+    """Plan over nchan channels: channel c owns visibilities offsets[c]:offsets[c+1] and grid c.
+
+    ``grid`` returns (nchan, N, N) grids and ``degrid`` takes them. ``tile`` = 0
+    picks the library default; :func:`autotune_batch` measures the candidates.
+    """
+
+    def __init__(self, table: Table, N: int, uv, offsets, precision: int = F32, tile: int = 0, stream=None):
+        torch = _torch()
+        _check_tensor(uv, "uv", torch.float64)
+        if uv.dim() != 2 or uv.shape[1] != 2:
+            raise ValueError("uv must be (nvis, 2)")
+        off = _offsets_array(offsets)
+        if off[-1] != uv.shape[0]:
+            raise ValueError(f"offsets end at {off[-1]} but uv holds {uv.shape[0]} visibilities")
+        self.lib = load()
+        self.table, self.N, self.precision = table, int(N), int(precision)
+        self.nvis = int(uv.shape[0])
+        self.device = uv.device
+        self.M = int(round(2 * table.x0 * N))
+        self.offsets = off
+        nb = ctypes.c_size_t()
+        _check(self.lib.lmg_batch_workspace_size(self.N, table.W, len(off) - 1, self.nvis, self.precision,
+                                                 ctypes.byref(nb)), "lmg_batch_workspace_size")
+        self.workspace = _bytes(nb.value, uv.device)
+        self.uv = uv
+        h = ctypes.c_void_p()
+        with torch.cuda.device(uv.device):
+            _check(self.lib.lmg_batch_plan_create(table.handle, self.N, self.precision, len(off) - 1,
+                                                  off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(uv),
+                                                  int(tile), _ptr(self.workspace), nb.value, _stream_handle(stream),
+                                                  ctypes.byref(h)), "lmg_batch_plan_create")
+        self._h = h
+        self._scratch = {}
+        self.nchan = len(off) - 1
+
+    def info(self):
+        d = super().info()
+        nc, t, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.lmg_batch_info(self._h, ctypes.byref(nc), ctypes.byref(t), ctypes.byref(w)), "lmg_batch_info")
+        d.update(channels=nc.value, waves=w.value)
+        return d
+
+
+_TUNED = {}
+
+
+def autotune_batch(table: Table, N: int, uv, offsets, vis, weights=None, precision: int = F32,
+                   tiles=(16, 32, 64), reps: int = 3, stream=None):
+    """Pick the uv tile edge of a batched plan by timing gridding + degridding on the caller's data.
+
+    Each candidate tile (skipped where the library rejects it) gets a plan, one
+    untimed grid + degrid, then ``reps`` timed ones (HIP events on the launch
+    stream). The fastest plan is returned with the timings {tile: ms}; the
+    choice is remembered for the same (N, W, precision, channels, visibilities).
+    """
+    torch = _torch()
+    off = _offsets_array(offsets)
+    key = (int(N), table.W, int(precision), len(off) - 1, int(uv.shape[0]))
+    if key in _TUNED:
+        return BatchPlan(table, N, uv, off, precision, _TUNED[key][0], stream), _TUNED[key][1]
+    s = torch.cuda.current_stream() if stream is None else stream
+    best, timings = None, {}
+    for T in tiles:
+        if T > N or N // T > 128:
+            continue
+        try:
+            plan = BatchPlan(table, N, uv, off, precision, T, stream)
+        except LmgError:
+            continue
+        g = plan.grid(vis, weights, stream=s)
+        v = plan.degrid(g, stream=s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            plan.grid(vis, weights, out=g, stream=s)
+            plan.degrid(g, out=v, stream=s)
+        e1.record(s)
+        e1.synchronize()
+        timings[T] = e0.elapsed_time(e1) / reps
+        if best is None or timings[T] < timings[best[0]]:
+            best = (T, plan)
+        del g, v
+    if best is None:
+        raise LmgError(-1, "autotune_batch: no tile edge is valid for this problem")
+    _TUNED[key] = (best[0], timings)
+    return best[1], timings
+
+
+def grid_batched(table: Table, N: int, uv, offsets, vis, weights=None, kahan: bool = False, stream=None):
+    """One-shot batched gridding (plan built and released inside); returns (nchan, N, N) grids."""
+    torch = _torch()
+    prec = _prec_of(vis.dtype, kahan)
+    off = _offsets_array(offsets)
+    nchan = len(off) - 1
+    lib = load()
+    nb = ctypes.c_size_t()
+    _check(lib.lmg_workspace_size_batched(int(N), table.W, nchan, int(off[-1]), prec, OP_GRID, ctypes.byref(nb)),
+           "lmg_workspace_size_batched")
+    ws = _bytes(nb.value, vis.device)
+    out = torch.empty((nchan, N, N), dtype=vis.dtype, device=vis.device)
+    _check(lib.lmg_grid_batched(table.handle, int(N), prec, nchan, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                _ptr(uv), _ptr(vis), _ptr(weights), _ptr(out), _ptr(ws), nb.value,
+                                _stream_handle(stream)), "lmg_grid_batched")
+    return out
+
+
+def degrid_batched(table: Table, N: int, uv, offsets, grids, stream=None):
+    """One-shot batched degridding of (nchan, N, N) grids."""
+    torch = _torch()
+    prec = _prec_of(grids.dtype, False)
+    off = _offsets_array(offsets)
+    nchan = len(off) - 1
+    lib = load()
+    nb = ctypes.c_size_t()
+    _check(lib.lmg_workspace_size_batched(int(N), table.W, nchan, int(off[-1]), prec, OP_DEGRID, ctypes.byref(nb)),
+           "lmg_workspace_size_batched")
+    ws = _bytes(nb.value, grids.device)
+    out = torch.empty(int(off[-1]), dtype=grids.dtype, device=grids.device)
+    _check(lib.lmg_degrid_batched(table.handle, int(N), prec, nchan, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  _ptr(uv), _ptr(grids), _ptr(out), _ptr(ws), nb.value, _stream_handle(stream)),
+           "lmg_degrid_batched")
+    return out
+
+
+# ------------------------------------------------------------ autograd
+# Gridding and degridding are transposes of each other (C is real), and so
+# are the dirty image and the prediction (the correction is a real diagonal,
+# the crop is the transpose of the zero pad, and the +i2pi transform is the
+# adjoint of the -i2pi one). Each backward is therefore the other call of the
+# same plan. Gradients follow torch's convention for complex tensors
+# (dL/dRe + i dL/dIm). Where weights are involved, the chain rule's product
+# with w, and the weight gradient Re(conj(V) * A^T g), are torch elementwise
+# ops on the backward's output.
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class _Degrid(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, grid_):
+            ctx.plan = plan
+            return plan.degrid(grid_.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return None, ctx.plan.grid(g.contiguous(), None)
+
+    class _Grid(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, vis, weights):
+            ctx.plan = plan
+            ctx.save_for_backward(vis, weights)
+            return plan.grid(vis.contiguous(), None if weights is None else weights.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            vis, weights = ctx.saved_tensors
+            d = ctx.plan.degrid(g.contiguous())
+            gv = d if weights is None else d * weights
+            gw = None
+            if weights is not None and ctx.needs_input_grad[2]:
+                gw = (vis.conj() * d).real.to(weights.dtype)
+            return None, (gv if ctx.needs_input_grad[1] else None), gw
+
+    class _Predict(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, image):
+            ctx.plan = plan
+            return plan.predict_visibilities(image.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            return None, ctx.plan.make_dirty_image(g.contiguous(), None)
+
+    class _Dirty(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, plan, vis, weights):
+            ctx.plan = plan
+            ctx.save_for_backward(vis, weights)
+            return plan.make_dirty_image(vis.contiguous(), None if weights is None else weights.contiguous())
+
+        @staticmethod
+        def backward(ctx, g):
+            vis, weights = ctx.saved_tensors
+            d = ctx.plan.predict_visibilities(g.contiguous())
+            gv = d if weights is None else d * weights
+            gw = None
+            if weights is not None and ctx.needs_input_grad[2]:
+                gw = (vis.conj() * d).real.to(weights.dtype)
+            return None, (gv if ctx.needs_input_grad[1] else None), gw
+
+    return _Degrid, _Grid, _Predict, _Dirty
+
+
+_AUTOGRAD = None
+
+
+def _fns():
+    global _AUTOGRAD
+    if _AUTOGRAD is None:
+        _AUTOGRAD = _autograd_function()
+    return _AUTOGRAD
+
+
+class Degrid:
+    """Differentiable degridding: ``Degrid.apply(plan, grid) -> vis``; backward = gridding of the gradient."""
+
+    @staticmethod
+    def apply(plan: "Plan", grid_):
+        return _fns()[0].apply(plan, grid_)
+
+
+class Grid:
+    """Differentiable gridding: ``Grid.apply(plan, vis, weights=None) -> grid``; backward = weighted degridding."""
+
+    @staticmethod
+    def apply(plan: "Plan", vis, weights=None):
+        return _fns()[1].apply(plan, vis, weights)
+
+
+class PredictVisibilities:
+    """Differentiable prediction: ``PredictVisibilities.apply(plan, image) -> vis``; backward = dirty image."""
+
+    @staticmethod
+    def apply(plan: "Plan", image):
+        return _fns()[2].apply(plan, image)
+
+
+class MakeDirtyImage:
+    """Differentiable dirty image: ``MakeDirtyImage.apply(plan, vis, weights=None)``; backward = prediction."""
+
+    @staticmethod
+    def apply(plan: "Plan", vis, weights=None):
+        return _fns()[3].apply(plan, vis, weights)
 
 
 # ------------------------------------------------------------ one-shot calls

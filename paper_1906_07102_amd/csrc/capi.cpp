@@ -32,6 +32,9 @@ struct lmg_plan {
     int max_items = 0;
     int cap = 0;
     int M = 0;                  // retained image size 2 x0 N
+    int waves = 0;              // waves (private LDS patches) per gridding workgroup
+    int nchan = 1;              // channels (grids), each with its own run of visibilities
+    int nblocks = 0;            // plan blocks (runs of <= kPlanBlockVis visibilities of one channel)
     bool bad_data = false;
     // Occupied band of the grid (storage rows / columns [lo, hi)) and the
     // window of tiles that covers it (first tile, number of tiles).
@@ -42,6 +45,8 @@ struct lmg_plan {
     int* tile_start = nullptr;
     int* item_start = nullptr;
     int* blockhist = nullptr;      // per plan block and tile: counts, then offsets
+    int4* blocks = nullptr;        // per plan block: (channel, first visibility, count, 0)
+    int* chan_blocks = nullptr;    // per channel, its first plan block; nchan + 1 entries
     int4* items = nullptr;
     int* inv0 = nullptr;           // caller index -> tile-order position (-1: dropped)
     uint16_t* loc0 = nullptr;      // first-tap cell within the tile, by position
@@ -91,37 +96,54 @@ int choose_tile(int N, lmg_precision prec) {
     return T;
 }
 
-// Largest tile <= T whose LDS patch and table fit one workgroup.
+// Largest tile <= T whose table and four private patches fit one
+// workgroup's LDS; where the tile cannot shrink (at most 128 x 128 tiles),
+// fewer waves per workgroup (fit_waves).
 int fit_tile(int T, int N, lmg_precision prec, int W, int Ms) {
-    while (T > 8 && grid_lds_bytes(prec, W, T, Ms) > kMaxLds && N / (T / 2) <= 128) T /= 2;
+    while (T > 8 && grid_lds_bytes(prec, W, T, Ms, kMaxGridWaves) > kMaxDynLds && N / (T / 2) <= 128) T /= 2;
     return T;
+}
+int fit_waves(int T, lmg_precision prec, int W, int Ms) {
+    int waves = kMaxGridWaves;
+    while (waves > 1 && grid_lds_bytes(prec, W, T, Ms, waves) > kMaxDynLds) --waves;
+    return waves;
 }
 
 int choose_cap() { return std::min(env_int("LMG_CAP", 8192), kMaxCap); }
+
+constexpr int kMaxChannels = 65536;
 
 size_t real_size(lmg_precision p) { return p == LMG_F64 ? 8 : 4; }
 size_t cplx_size(lmg_precision p) { return 2 * real_size(p); }
 size_t patch_cell_size(lmg_precision p) { return p == LMG_F32 ? 8 : 16; }
 
 struct Layout {
-    size_t flags, tile_count, tile_start, item_start, blockhist, items, inv0, loc0, dlt0, dlt, pos2, inv, pieces, coef,
-        twiddle, hpix, total;
+    size_t flags, tile_count, tile_start, item_start, blockhist, blocks, chan_blocks, items, inv0, loc0, dlt0, dlt, pos2,
+        inv, pieces, coef, twiddle, hpix, total;
     int max_items;
+    int max_blocks;
 };
+
+// Most plan blocks for nvis visibilities over nchan channels.
+int64_t max_plan_blocks(int64_t nvis, int nchan) { return plan_blocks(nvis) + nchan; }
 
 // Tile arrays are sized for the smallest tile any plan may pick (N / T <= 128,
 // T >= 8), so the size query need not know the table.
-Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap) {
+Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap, int nchan = 1) {
     Layout L{};
     const int64_t ntiles = std::min<int64_t>(16384, static_cast<int64_t>(N / 8) * (N / 8));
-    L.max_items = static_cast<int>(std::min<int64_t>(ntiles, nvis) + (nvis + cap - 1) / cap + 1);
+    const int64_t tot = ntiles * nchan;
+    L.max_items = static_cast<int>(std::min<int64_t>(tot, nvis) + (nvis + cap - 1) / cap + 1);
+    L.max_blocks = static_cast<int>(max_plan_blocks(nvis, nchan));
     size_t o = 0;
     auto take = [&o](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     L.flags = take(16 * sizeof(int));
-    L.tile_count = take(ntiles * sizeof(int));
-    L.tile_start = take((ntiles + 1) * sizeof(int));
-    L.item_start = take((ntiles + 1) * sizeof(int));
-    L.blockhist = take(static_cast<size_t>(plan_blocks(nvis)) * ntiles * sizeof(int));
+    L.tile_count = take(tot * sizeof(int));
+    L.tile_start = take((tot + 1) * sizeof(int));
+    L.item_start = take((tot + 1) * sizeof(int));
+    L.blockhist = take(static_cast<size_t>(L.max_blocks) * ntiles * sizeof(int));
+    L.blocks = take(static_cast<size_t>(L.max_blocks) * sizeof(int4));
+    L.chan_blocks = take((static_cast<size_t>(nchan) + 1) * sizeof(int));
     L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
     L.inv0 = take(static_cast<size_t>(nvis) * sizeof(int));
     L.loc0 = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
@@ -137,10 +159,11 @@ Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap) {
     return L;
 }
 
-// Scratch of a planned call: [grid][fft tmp][visibilities in plan order][patches].
+// Scratch of a planned call: [work counters][grid][fft tmp][visibilities in plan order][patches].
 struct Scratch {
-    size_t grid, tmp, vs, patches, total;
+    size_t counters, grid, tmp, vs, patches, total;
 };
+constexpr int kCounters = 2;    // work-item counters of the gridding and degridding kernels
 
 Scratch scratch_layout(int N, int W, int T, int M, int items, int64_t nvis, lmg_precision prec, int op) {
     const size_t P = static_cast<size_t>(T + W - 1);
@@ -149,7 +172,8 @@ Scratch scratch_layout(int N, int W, int T, int M, int items, int64_t nvis, lmg_
     const size_t tmp = align_up(static_cast<size_t>(M) * N * cplx_size(prec));
     const size_t vs = align_up(static_cast<size_t>(nvis) * cplx_size(prec));
     Scratch s{};
-    size_t o = 0;
+    size_t o = align_up(kCounters * sizeof(int));
+    s.counters = 0;
     const bool image = op == LMG_OP_DIRTY || op == LMG_OP_PREDICT;
     if (image) { s.grid = o; o += grid; s.tmp = o; o += tmp; }
     s.vs = o;
@@ -247,23 +271,24 @@ void set_band(lmg_plan* p, int rmin, int rmax, int cmin, int cmax) {
 }
 
 lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
-                    hipStream_t s, bool band_only = false) {
+                    int* counters, hipStream_t s, bool band_only = false) {
     const lmg_table* t = p->table;
+    LMG_HIP(launch_zero_ints(counters, kCounters, s));
     {
         TraceScope ts("permute_in", s);
         LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vs, s));
     }
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
-    a.n_items = p->n_items; a.dlo = delta_low(t->W);
+    a.n_items = p->n_items; a.waves = p->waves; a.dlo = delta_low(t->W);
     a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
-    a.vis = vs; a.patches = patches;
+    a.vis = vs; a.patches = patches; a.counter = counters;
     {
         TraceScope ts("grid_items", s);
         LMG_HIP(launch_grid(p->prec, a, s));
     }
     AssembleArgs b{};
-    b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx;
+    b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx; b.nchan = p->nchan;
     if (band_only) {                  // an internal grid: only the occupied window is ever read
         b.tr0 = p->win_r0; b.trows = p->win_rn; b.tc0 = p->win_c0; b.tcols = p->win_cn;
     } else {
@@ -275,13 +300,14 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     return LMG_OK;
 }
 
-lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, hipStream_t s) {
+lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, int* counters, hipStream_t s) {
     const lmg_table* t = p->table;
+    LMG_HIP(launch_zero_ints(counters + 1, 1, s));
     DegridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
     a.n_items = p->n_items; a.dlo = delta_low(t->W);
     a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
-    a.grid = grid; a.vis_out = vs;
+    a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
     {
         TraceScope ts("degrid_items", s);
         LMG_HIP(launch_degrid(p->prec, a, s));
@@ -308,6 +334,132 @@ bool scratch_ok(const lmg_plan* p, int op, void* scratch, size_t bytes) {
     return need == 0 || (scratch && bytes >= need);
 }
 
+// Plan for nchan channels; channel c owns visibilities [offsets[c], offsets[c + 1]) and grid c.
+// tile = 0 picks the default tile edge; otherwise a power of two in [8, min(128, N)] with N / tile <= 128.
+lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                       const double* uv, int tile, void* workspace, size_t ws_bytes, void* stream, lmg_plan** out) {
+    int M = 0;
+    if (!table || !out || !offsets || prec < LMG_F32 || prec > LMG_F64 || nchan < 1 || nchan > kMaxChannels ||
+        !valid_grid(N, table->W, table->x0, &M))
+        return LMG_EINVAL;
+    if (offsets[0] != 0) return LMG_EINVAL;
+    for (int c = 0; c < nchan; ++c)
+        if (offsets[c + 1] < offsets[c]) return LMG_EINVAL;
+    const int64_t nvis = offsets[nchan];
+    if (nvis < 0 || nvis > INT32_MAX || (nvis > 0 && !uv)) return LMG_EINVAL;
+    if (tile != 0 && (!is_pow2(tile) || tile < 8 || tile > 128 || tile > N || N / tile > 128)) return LMG_EINVAL;
+    const size_t tab_bytes = (prec == LMG_F64 ? table->coef64.size() * 8 : table->coef32.size() * 4);
+    if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
+    const int T = tile ? tile : fit_tile(choose_tile(N, prec), N, prec, table->W, table->Ms);
+    const int waves = fit_waves(T, prec, table->W, table->Ms);
+    if (grid_lds_bytes(prec, table->W, T, table->Ms, waves) > kMaxDynLds) return LMG_ENOTSUP;
+    const int cap = choose_cap();
+    const Layout L = plan_layout(N, nvis, prec, cap, nchan);
+    if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
+    if (ensure_attributes() != hipSuccess) return LMG_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::unique_ptr<lmg_plan> p(new (std::nothrow) lmg_plan);
+    if (!p) return LMG_EINVAL;
+    char* base = static_cast<char*>(workspace);
+    p->table = table;
+    p->prec = prec;
+    p->g.N = N; p->g.W = table->W; p->g.T = T; p->g.ntx = N / T; p->g.ntiles = (N / T) * (N / T);
+    p->g.nchan = nchan;
+    p->g.ref = tap_reference(table->W);
+    p->waves = waves;
+    p->nchan = nchan;
+    p->nvis = nvis;
+    p->cap = cap;
+    p->max_items = L.max_items;
+    p->M = M;
+    p->flags = reinterpret_cast<int*>(base + L.flags);
+    p->tile_count = reinterpret_cast<int*>(base + L.tile_count);
+    p->tile_start = reinterpret_cast<int*>(base + L.tile_start);
+    p->item_start = reinterpret_cast<int*>(base + L.item_start);
+    p->blockhist = reinterpret_cast<int*>(base + L.blockhist);
+    p->blocks = reinterpret_cast<int4*>(base + L.blocks);
+    p->chan_blocks = reinterpret_cast<int*>(base + L.chan_blocks);
+    p->items = reinterpret_cast<int4*>(base + L.items);
+    p->inv0 = reinterpret_cast<int*>(base + L.inv0);
+    p->loc0 = reinterpret_cast<uint16_t*>(base + L.loc0);
+    p->dlt0 = base + L.dlt0;
+    p->dlt = base + L.dlt;
+    p->pos2 = reinterpret_cast<int*>(base + L.pos2);
+    p->inv = reinterpret_cast<int*>(base + L.inv);
+    p->pieces = reinterpret_cast<int2*>(base + L.pieces);
+    p->coef = base + L.coef;
+    p->twiddle = base + L.twiddle;
+    p->hpix = base + L.hpix;
+
+    // Plan blocks: runs of at most kPlanBlockVis visibilities of one channel.
+    std::vector<int4> blocks;
+    std::vector<int> chan_blocks(static_cast<size_t>(nchan) + 1);
+    for (int c = 0; c < nchan; ++c) {
+        chan_blocks[c] = static_cast<int>(blocks.size());
+        for (int64_t a = offsets[c]; a < offsets[c + 1]; a += kPlanBlockVis)
+            blocks.push_back(make_int4(c, static_cast<int>(a),
+                                       static_cast<int>(std::min<int64_t>(kPlanBlockVis, offsets[c + 1] - a)), 0));
+    }
+    chan_blocks[nchan] = static_cast<int>(blocks.size());
+    p->nblocks = static_cast<int>(blocks.size());
+    if (p->nblocks > L.max_blocks) return LMG_EINVAL;       // cannot happen; guards the workspace bound
+
+    // Constant tables: kernel coefficients, FFT twiddles, correction h(x_p); block tables.
+    std::vector<double> h(N);
+    if (lmg_correction(table, N, h.data()) != LMG_OK) return LMG_EINVAL;
+    std::vector<float> hf(h.begin(), h.end());
+    if (prec == LMG_F64) {
+        if (upload(p->coef, table->coef64.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->twiddle, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->hpix, h.data(), sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
+    } else {
+        if (upload(p->coef, table->coef32.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->twiddle, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->hpix, hf.data(), sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
+    }
+    if (!blocks.empty() && upload(p->blocks, blocks.data(), blocks.size() * sizeof(int4), s) != LMG_OK)
+        return LMG_EHIP;
+    if (upload(p->chan_blocks, chan_blocks.data(), chan_blocks.size() * sizeof(int), s) != LMG_OK) return LMG_EHIP;
+    LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
+    {
+        TraceScope ts("plan_count", s);
+        LMG_HIP(launch_plan_count(uv, p->blocks, p->nblocks, p->g, p->blockhist, p->flags, s));
+    }
+    {
+        TraceScope ts("plan_colscan", s);
+        LMG_HIP(launch_plan_colscan(p->g, p->blockhist, p->chan_blocks, p->tile_count, s));
+    }
+    {
+        TraceScope ts("plan_scan", s);
+        LMG_HIP(launch_plan_scan(p->g, p->tile_count, p->tile_start, p->item_start, p->items, p->flags, cap, s));
+    }
+    {
+        TraceScope ts("plan_scatter", s);
+        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, p->blocks, p->nblocks, p->g, p->tile_start, p->blockhist,
+                                    p->inv0, p->loc0, p->dlt0, s));
+    }
+    {
+        TraceScope ts("plan_sort_items", s);
+        LMG_HIP(launch_plan_sort(prec == LMG_F64, p->g, p->items, L.max_items, p->flags, p->loc0, p->dlt0, p->dlt,
+                                 p->pos2, p->pieces, s));
+    }
+    {
+        TraceScope ts("plan_compose", s);
+        LMG_HIP(launch_plan_compose(p->inv0, p->pos2, nvis, p->inv, s));
+    }
+    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
+    LMG_HIP(hipStreamSynchronize(s));           // also keeps the uploaded host vectors alive until copied
+    p->bad_data = flags[0] != 0;
+    p->n_items = flags[1];
+    p->n_valid = flags[2];
+    p->n_busy = flags[3];
+    set_band(p.get(), flags[4], flags[5], flags[6], flags[7]);
+    if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
+    *out = p.release();
+    return LMG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -322,98 +474,29 @@ lmg_status lmg_plan_workspace_size(int N, int W, int64_t nvis, lmg_precision pre
 
 lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, int64_t nvis, const double* uv,
                            void* workspace, size_t ws_bytes, void* stream, lmg_plan** out) {
-    int M = 0;
-    if (!table || !out || prec < LMG_F32 || prec > LMG_F64 || nvis < 0 || nvis > INT32_MAX ||
-        !valid_grid(N, table->W, table->x0, &M) || (nvis > 0 && !uv))
-        return LMG_EINVAL;
-    const size_t tab_bytes = (prec == LMG_F64 ? table->coef64.size() * 8 : table->coef32.size() * 4);
-    if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
-    const int T = fit_tile(choose_tile(N, prec), N, prec, table->W, table->Ms);
-    if (grid_lds_bytes(prec, table->W, T, table->Ms) > kMaxLds) return LMG_ENOTSUP;
-    const int cap = choose_cap();
-    const Layout L = plan_layout(N, nvis, prec, cap);
-    if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
-    if (ensure_attributes() != hipSuccess) return LMG_EHIP;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    std::unique_ptr<lmg_plan> p(new (std::nothrow) lmg_plan);
-    if (!p) return LMG_EINVAL;
-    char* base = static_cast<char*>(workspace);
-    p->table = table;
-    p->prec = prec;
-    p->g.N = N; p->g.W = table->W; p->g.T = T; p->g.ntx = N / T; p->g.ntiles = (N / T) * (N / T);
-    p->g.ref = tap_reference(table->W);
-    p->nvis = nvis;
-    p->cap = cap;
-    p->max_items = L.max_items;
-    p->M = M;
-    p->flags = reinterpret_cast<int*>(base + L.flags);
-    p->tile_count = reinterpret_cast<int*>(base + L.tile_count);
-    p->tile_start = reinterpret_cast<int*>(base + L.tile_start);
-    p->item_start = reinterpret_cast<int*>(base + L.item_start);
-    p->blockhist = reinterpret_cast<int*>(base + L.blockhist);
-    p->items = reinterpret_cast<int4*>(base + L.items);
-    p->inv0 = reinterpret_cast<int*>(base + L.inv0);
-    p->loc0 = reinterpret_cast<uint16_t*>(base + L.loc0);
-    p->dlt0 = base + L.dlt0;
-    p->dlt = base + L.dlt;
-    p->pos2 = reinterpret_cast<int*>(base + L.pos2);
-    p->inv = reinterpret_cast<int*>(base + L.inv);
-    p->pieces = reinterpret_cast<int2*>(base + L.pieces);
-    p->coef = base + L.coef;
-    p->twiddle = base + L.twiddle;
-    p->hpix = base + L.hpix;
+    const int64_t offsets[2] = {0, nvis};
+    return create_plan(table, N, prec, 1, offsets, uv, 0, workspace, ws_bytes, stream, out);
+}
 
-    // Constant tables: kernel coefficients, FFT twiddles, correction h(x_p).
-    std::vector<double> h(N);
-    if (lmg_correction(table, N, h.data()) != LMG_OK) return LMG_EINVAL;
-    if (prec == LMG_F64) {
-        if (upload(p->coef, table->coef64.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
-        if (upload(p->twiddle, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
-        if (upload(p->hpix, h.data(), sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
-    } else {
-        std::vector<float> hf(h.begin(), h.end());
-        if (upload(p->coef, table->coef32.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
-        if (upload(p->twiddle, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
-        if (upload(p->hpix, hf.data(), sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
-        LMG_HIP(hipStreamSynchronize(s));       // hf goes out of scope
-    }
-    LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
-    {
-        TraceScope ts("plan_count", s);
-        LMG_HIP(launch_plan_count(uv, nvis, p->g, p->blockhist, p->flags, s));
-    }
-    {
-        TraceScope ts("plan_colscan", s);
-        LMG_HIP(launch_plan_colscan(p->g, p->blockhist, plan_blocks(nvis), p->tile_count, s));
-    }
-    {
-        TraceScope ts("plan_scan", s);
-        LMG_HIP(launch_plan_scan(p->g, p->tile_count, p->tile_start, p->item_start, p->items, p->flags, cap, s));
-    }
-    {
-        TraceScope ts("plan_scatter", s);
-        LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, nvis, p->g, p->tile_start, p->blockhist, p->inv0, p->loc0,
-                                    p->dlt0, s));
-    }
-    {
-        TraceScope ts("plan_sort_items", s);
-        LMG_HIP(launch_plan_sort(prec == LMG_F64, p->g, p->items, L.max_items, p->flags, p->loc0, p->dlt0, p->dlt,
-                                 p->pos2, p->pieces, s));
-    }
-    {
-        TraceScope ts("plan_compose", s);
-        LMG_HIP(launch_plan_compose(p->inv0, p->pos2, nvis, p->inv, s));
-    }
-    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
-    LMG_HIP(hipStreamSynchronize(s));
-    p->bad_data = flags[0] != 0;
-    p->n_items = flags[1];
-    p->n_valid = flags[2];
-    p->n_busy = flags[3];
-    set_band(p.get(), flags[4], flags[5], flags[6], flags[7]);
-    if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
-    *out = p.release();
+lmg_status lmg_batch_workspace_size(int N, int W, int nchan, int64_t nvis, lmg_precision prec, size_t* bytes) {
+    if (!bytes || !is_pow2(N) || N < 64 || N > 8192 || W < 1 || W > kMaxW || nchan < 1 || nchan > kMaxChannels ||
+        nvis < 0 || nvis > INT32_MAX || prec < LMG_F32 || prec > LMG_F64)
+        return LMG_EINVAL;
+    *bytes = plan_layout(N, nvis, prec, choose_cap(), nchan).total;
+    return LMG_OK;
+}
+
+lmg_status lmg_batch_plan_create(const lmg_table* table, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                                 const double* uv, int tile, void* workspace, size_t ws_bytes, void* stream,
+                                 lmg_plan** out) {
+    return create_plan(table, N, prec, nchan, offsets, uv, tile, workspace, ws_bytes, stream, out);
+}
+
+lmg_status lmg_batch_info(const lmg_plan* p, int* nchan, int* tile, int* waves) {
+    if (!p) return LMG_EINVAL;
+    if (nchan) *nchan = p->nchan;
+    if (tile) *tile = p->g.T;
+    if (waves) *waves = p->waves;
     return LMG_OK;
 }
 
@@ -447,7 +530,8 @@ lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, 
     if (!scratch_ok(p, LMG_OP_GRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     const Scratch L = plan_scratch(p, LMG_OP_GRID);
     char* sc = static_cast<char*>(scratch);
-    return run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, static_cast<hipStream_t>(stream));
+    return run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, reinterpret_cast<int*>(sc + L.counters),
+                    static_cast<hipStream_t>(stream));
 }
 
 lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out, void* scratch, size_t scratch_bytes,
@@ -455,12 +539,15 @@ lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out
     if (!p || !grid || (p->nvis > 0 && !vis_out)) return LMG_EINVAL;
     if (!scratch_ok(p, LMG_OP_DEGRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     const Scratch L = plan_scratch(p, LMG_OP_DEGRID);
-    return run_degrid(p, grid, vis_out, static_cast<char*>(scratch) + L.vs, static_cast<hipStream_t>(stream));
+    char* sc = static_cast<char*>(scratch);
+    return run_degrid(p, grid, vis_out, sc + L.vs, reinterpret_cast<int*>(sc + L.counters),
+                      static_cast<hipStream_t>(stream));
 }
 
 lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image, void* scratch,
                                         size_t scratch_bytes, void* stream) {
     if (!p || !image || (p->nvis > 0 && !vis)) return LMG_EINVAL;
+    if (p->nchan != 1) return LMG_ENOTSUP;
     if (!scratch_ok(p, LMG_OP_DIRTY, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int N = p->g.N, M = p->M;
@@ -468,13 +555,14 @@ lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, cons
     char* sc = static_cast<char*>(scratch);
     void* grid = sc + L.grid;
     void* tmp = sc + L.tmp;
-    lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, s, true);
+    lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, reinterpret_cast<int*>(sc + L.counters), s,
+                             true);
     if (st != LMG_OK) return st;
     const bool f64 = p->prec == LMG_F64;
     const size_t cs = cplx_size(p->prec);
     const int r0 = p->band_r0, nr = p->band_r1 - p->band_r0, c0 = p->band_c0, nc = p->band_c1 - p->band_c0;
     if (nr == 0) {                     // nothing gridded: the image is zero
-        LMG_HIP(hipMemsetAsync(image, 0, static_cast<size_t>(M) * M * cs, s));
+        LMG_HIP(launch_zero_ints(static_cast<int*>(image), static_cast<int>(static_cast<size_t>(M) * M * cs / 4), s));
         return LMG_OK;
     }
     // Rows m of the occupied band: transform over n (only the occupied columns are non-zero), keep the
@@ -503,6 +591,7 @@ lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, cons
 lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image, void* vis_out, void* scratch,
                                             size_t scratch_bytes, void* stream) {
     if (!p || !image || (p->nvis > 0 && !vis_out)) return LMG_EINVAL;
+    if (p->nchan != 1) return LMG_ENOTSUP;
     if (!scratch_ok(p, LMG_OP_PREDICT, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int N = p->g.N, M = p->M;
@@ -534,7 +623,7 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
             LMG_HIP(launch_fft_pass(f64, b, s));
         }
     }
-    return run_degrid(p, grid, vis_out, sc + L.vs, s);
+    return run_degrid(p, grid, vis_out, sc + L.vs, reinterpret_cast<int*>(sc + L.counters), s);
 }
 
 lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes) {
@@ -565,6 +654,26 @@ lmg_status one_shot(const lmg_table* t, int N, lmg_precision prec, int64_t nvis,
     lmg_plan_workspace_size(N, t->W, nvis, prec, &pbytes);
     lmg_plan* p = nullptr;
     st = lmg_plan_create(t, N, prec, nvis, uv, ws, pbytes, stream, &p);
+    if (st != LMG_OK) return st;
+    st = body(p, static_cast<char*>(ws) + pbytes, ws_bytes - pbytes);
+    lmg_plan_destroy(p);
+    return st;
+}
+
+// Batched one-shot calls use the default tile edge for N (not shrunk to the
+// table: fewer waves per workgroup instead), so that the size query is exact.
+template <typename F>
+lmg_status one_shot_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                            const double* uv, void* ws, size_t ws_bytes, void* stream, int op, F&& body) {
+    if (!t || !offsets || nchan < 1) return LMG_EINVAL;
+    size_t need = 0;
+    lmg_status st = lmg_workspace_size_batched(N, t->W, nchan, offsets[nchan], prec, op, &need);
+    if (st != LMG_OK) return st;
+    if (!ws || ws_bytes < need) return LMG_EWORKSPACE;
+    size_t pbytes = 0;
+    lmg_batch_workspace_size(N, t->W, nchan, offsets[nchan], prec, &pbytes);
+    lmg_plan* p = nullptr;
+    st = create_plan(t, N, prec, nchan, offsets, uv, choose_tile(N, prec), ws, pbytes, stream, &p);
     if (st != LMG_OK) return st;
     st = body(p, static_cast<char*>(ws) + pbytes, ws_bytes - pbytes);
     lmg_plan_destroy(p);
@@ -601,6 +710,36 @@ lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision pre
                     [&](lmg_plan* p, void* sc, size_t sb) {
                         return lmg_predict_visibilities_planned(p, image, vis_out, sc, sb, stream);
                     });
+}
+
+lmg_status lmg_workspace_size_batched(int N, int W, int nchan, int64_t nvis, lmg_precision prec, int op,
+                                      size_t* bytes) {
+    size_t plan = 0;
+    if (op != LMG_OP_GRID && op != LMG_OP_DEGRID) return LMG_EINVAL;
+    lmg_status st = lmg_batch_workspace_size(N, W, nchan, nvis, prec, &plan);
+    if (st != LMG_OK) return st;
+    const int T = choose_tile(N, prec);
+    const Layout L = plan_layout(N, nvis, prec, choose_cap(), nchan);
+    *bytes = plan + scratch_for(N, W, T, 0, L.max_items, nvis, prec, op);
+    return LMG_OK;
+}
+
+lmg_status lmg_grid_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                            const double* uv, const void* vis, const float* w, void* grids, void* ws,
+                            size_t ws_bytes, void* stream) {
+    return one_shot_batched(t, N, prec, nchan, offsets, uv, ws, ws_bytes, stream, LMG_OP_GRID,
+                            [&](lmg_plan* p, void* sc, size_t sb) {
+                                return lmg_grid_planned(p, vis, w, grids, sc, sb, stream);
+                            });
+}
+
+lmg_status lmg_degrid_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,
+                              const double* uv, const void* grids, void* vis_out, void* ws, size_t ws_bytes,
+                              void* stream) {
+    return one_shot_batched(t, N, prec, nchan, offsets, uv, ws, ws_bytes, stream, LMG_OP_DEGRID,
+                            [&](lmg_plan* p, void* sc, size_t sb) {
+                                return lmg_degrid_planned(p, grids, vis_out, sc, sb, stream);
+                            });
 }
 
 lmg_status lmg_fft2_centred(int N, lmg_precision prec, int sign, void* data, void* scratch, void* stream) {

@@ -10,7 +10,8 @@
 namespace lmg {
 
 // The plan's streaming passes over the visibilities: blocks of kPlanThreads
-// threads, each handling kPlanBlockVis consecutive visibilities.
+// threads, each handling a run of at most kPlanBlockVis consecutive
+// visibilities of one channel.
 constexpr int kPlanThreads = 1024;
 constexpr int kPlanBlockVis = 65536;
 inline int plan_blocks(int64_t nvis) { return static_cast<int>((nvis + kPlanBlockVis - 1) / kPlanBlockVis); }
@@ -24,12 +25,14 @@ struct PlanGeom {
     int W;        // support
     int T;        // tile edge (cells)
     int ntx;      // tiles per axis, N / T
-    int ntiles;   // ntx * ntx
+    int ntiles;   // ntx * ntx, per channel
+    int nchan;    // channels, each with its own grid; global tile = channel * ntiles + tile
     double ref;   // offset of the reference tap from the first tap
 };
 
 struct GridArgs {
     int N, W, T, ntx, Ms, degree, n_items;
+    int waves;             // waves per workgroup, 1..4, each with its own LDS patch
     double dlo;
     const int4* items;     // (tile, first position, count, pieces)
     const int2* pieces;    // (first entry, length | cell << 16)
@@ -37,10 +40,11 @@ struct GridArgs {
     const void* coef;      // coefficient table, float or double
     const void* vis;       // complex, entry order, weights applied
     void* patches;         // n_items patches of (T + W - 1)^2 cells
+    int* counter;          // work-item counter, zero at launch
 };
 
 struct AssembleArgs {
-    int N, W, T, ntx;
+    int N, W, T, ntx, nchan;
     int tr0, tc0, trows, tcols;   // window of tiles written (rows tr0.., columns tc0.., wrapping)
     const int* item_start;   // per tile, ntiles + 1
     const void* patches;
@@ -54,8 +58,9 @@ struct DegridArgs {
     const int2* pieces;
     const void* dlt;
     const void* coef;
-    const void* grid;
+    const void* grid;      // nchan grids of N x N
     void* vis_out;         // entry order
+    int* counter;          // work-item counter, zero at launch
 };
 
 struct FftArgs {
@@ -75,19 +80,22 @@ struct FftArgs {
     int row_off;
 };
 
-hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* blockhist, int* flags,
-                             hipStream_t s);
-hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, int nb, int* tile_count, hipStream_t s);
+hipError_t launch_plan_count(const double* uv, const int4* blocks, int nb, const PlanGeom& g, int* blockhist,
+                             int* flags, hipStream_t s);
+hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* chan_blocks, int* tile_count,
+                               hipStream_t s);
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
                             int* flags, int cap, hipStream_t s);
-hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               const int* blockhist, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s);
+hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
+                               const int* tile_start, const int* blockhist, int* inv, uint16_t* loc0, void* dlt0,
+                               hipStream_t s);
 hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
                             const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
                             hipStream_t s);
 hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s);
 hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const int* inv, int64_t nvis, void* vs,
                              hipStream_t s);
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s);
 hipError_t launch_permute_out(bool f64, const void* vs, const int* inv, int64_t nvis, void* out, hipStream_t s);
 hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s);
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s);
@@ -95,8 +103,13 @@ hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s)
 hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s);
 int fft_rows_per_block(int N, bool f64);
 hipError_t set_kernel_attributes();
-// LDS bytes of the gridding kernel (the degridding kernel needs no more).
-size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms);
+// LDS bytes of the gridding kernel with `waves` private patches (the
+// degridding kernel needs no more than one patch).
+size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms, int waves);
+constexpr int kMaxGridWaves = 4;
 constexpr size_t kMaxLds = 160 * 1024;
+// Dynamic LDS the item kernels may request: they also hold a few bytes of
+// static LDS (the current work item), and both must fit the 160 KB.
+constexpr size_t kMaxDynLds = kMaxLds - 256;
 
 }  // namespace lmg

@@ -24,6 +24,8 @@
 
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace lmg {
 namespace dev {
 
@@ -80,30 +82,32 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- plan
-// Pass 1: validate coordinates and count visibilities per tile, per block of
-// kPlanBlockVis visibilities (kept per block, so that pass 3 can place each
-// block's visibilities of a tile in one contiguous run).
-__global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __restrict__ uv, int64_t nvis, PlanGeom g,
-                                                             int* __restrict__ blockhist, int nb,
+// Pass 1: validate coordinates and count visibilities per tile, per plan
+// block (a run of at most kPlanBlockVis visibilities of one channel, kept
+// per block so that pass 3 can place each block's visibilities of a tile in
+// one contiguous run). blocks[b] = (channel, first visibility, count, 0).
+__global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __restrict__ uv, const int4* __restrict__ blocks,
+                                                             int nb, PlanGeom g, int* __restrict__ blockhist,
                                                              int* __restrict__ flags) {
     extern __shared__ int hist[];
     for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) hist[t] = 0;
     __syncthreads();
     const int chunk = xcd_chunk(blockIdx.x, nb);
-    const int64_t base = static_cast<int64_t>(chunk) * kPlanBlockVis;
+    const int4 bd = blocks[chunk];
+    const int64_t base = bd.y, end = static_cast<int64_t>(bd.y) + bd.z;
     int bad = 0;
     constexpr int kB = 8;
-    for (int i0 = 0; i0 < kPlanBlockVis; i0 += kB * kPlanThreads) {
+    for (int i0 = 0; i0 < bd.z; i0 += kB * kPlanThreads) {
         double2 c[kB];
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
-            if (k < nvis) c[u] = uv[k];
+            if (k < end) c[u] = uv[k];
         }
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
-            if (k >= nvis) break;
+            if (k >= end) break;
             int cu, cv;
             double du, dv;
             if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv))
@@ -118,19 +122,23 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __re
     for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) row[t] = hist[t];
 }
 
-// Pass 1b: per tile, the exclusive prefix of the block counts (in place) and the total.
-__global__ __launch_bounds__(256) void k_plan_colscan(PlanGeom g, int* __restrict__ blockhist, int nb,
+// Pass 1b: per (channel, tile), the exclusive prefix of the channel's block
+// counts (in place) and the total. Channel c owns blocks
+// [chan_blocks[c], chan_blocks[c + 1]); global tile = c * ntiles + tile.
+__global__ __launch_bounds__(256) void k_plan_colscan(PlanGeom g, int* __restrict__ blockhist,
+                                                      const int* __restrict__ chan_blocks,
                                                       int* __restrict__ tile_count) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= g.ntiles) return;
+    const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gt >= static_cast<int64_t>(g.ntiles) * g.nchan) return;
+    const int c = static_cast<int>(gt / g.ntiles), t = static_cast<int>(gt % g.ntiles);
     int run = 0;
-    for (int c = 0; c < nb; ++c) {
-        int* p = blockhist + static_cast<size_t>(c) * g.ntiles + t;
+    for (int b = chan_blocks[c]; b < chan_blocks[c + 1]; ++b) {
+        int* p = blockhist + static_cast<size_t>(b) * g.ntiles + t;
         const int x = *p;
         *p = run;
         run += x;
     }
-    tile_count[t] = run;
+    tile_count[gt] = run;
 }
 
 // Pass 2 (one workgroup): tile offsets, work items, cursors.
@@ -139,7 +147,7 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
                                                     int4* __restrict__ items, int* __restrict__ flags, int cap) {
     __shared__ int part[1024];
     __shared__ int part2[1024];
-    const int nt = g.ntiles;
+    const int nt = g.ntiles * g.nchan;          // global tiles, channel-major
     const int per = (nt + blockDim.x - 1) / blockDim.x;
     const int lo = threadIdx.x * per, hi = min(nt, lo + per);
     int s = 0, si = 0;
@@ -175,10 +183,11 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
         tile_start[t] = s;
         item_start[t] = si;
         if (c > 0) {
-            rmin = min(rmin, t / g.ntx);
-            rmax = max(rmax, t / g.ntx);
-            cmin = min(cmin, t % g.ntx);
-            cmax = max(cmax, t % g.ntx);
+            const int lt = t % g.ntiles;
+            rmin = min(rmin, lt / g.ntx);
+            rmax = max(rmax, lt / g.ntx);
+            cmin = min(cmin, lt % g.ntx);
+            cmax = max(cmax, lt % g.ntx);
         }
         for (int q = 0; q < ni; ++q) {
             const int a = static_cast<int>((static_cast<int64_t>(c) * q) / ni);
@@ -222,29 +231,32 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
 // Pass 3: give each visibility its tile-order position; store its local
 // first-tap cell and offsets there, and the position under its caller index.
 template <typename R>
-__global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __restrict__ uv, int64_t nvis,
-                                                               PlanGeom g, const int* __restrict__ tile_start,
-                                                               const int* __restrict__ blockhist, int nb,
+__global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __restrict__ uv,
+                                                               const int4* __restrict__ blocks, int nb, PlanGeom g,
+                                                               const int* __restrict__ tile_start,
+                                                               const int* __restrict__ blockhist,
                                                                int* __restrict__ inv, uint16_t* __restrict__ loc0,
                                                                typename C2<R>::T* __restrict__ dlt0) {
     extern __shared__ int cur[];
     const int chunk = xcd_chunk(blockIdx.x, nb);
+    const int4 bd = blocks[chunk];
     const int* row = blockhist + static_cast<size_t>(chunk) * g.ntiles;
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) cur[t] = tile_start[t] + row[t];
+    const int* ts = tile_start + static_cast<size_t>(bd.x) * g.ntiles;
+    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) cur[t] = ts[t] + row[t];
     __syncthreads();
-    const int64_t base = static_cast<int64_t>(chunk) * kPlanBlockVis;
+    const int64_t base = bd.y, end = static_cast<int64_t>(bd.y) + bd.z;
     constexpr int kB = 8;                                    // coordinates loaded together per thread
-    for (int i0 = 0; i0 < kPlanBlockVis; i0 += kB * kPlanThreads) {
+    for (int i0 = 0; i0 < bd.z; i0 += kB * kPlanThreads) {
         double2 c[kB];
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
-            if (k < nvis) c[u] = uv[k];
+            if (k < end) c[u] = uv[k];
         }
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
-            if (k >= nvis) break;
+            if (k >= end) break;
             int cu, cv;
             double du, dv;
             if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv)) {
@@ -262,7 +274,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
     }
 }
 
-// Pass 4 (one workgroup per item): order the item's visibilities by
+// Pass 4 (workgroups loop over items): order the item's visibilities by
 // footprint cell (counting sort in LDS) and cut each cell's run into pieces
 // of at most kPiece. Full pieces come first, interleaved over cells (all
 // first pieces of every cell, then all second pieces, ...) so that lanes of
@@ -276,7 +288,6 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
                                                          const typename C2<R>::T* __restrict__ dlt0,
                                                          typename C2<R>::T* __restrict__ dlt,
                                                          int* __restrict__ pos2, int2* __restrict__ pieces) {
-    if (static_cast<int>(blockIdx.x) >= flags[1]) return;
     extern __shared__ int sm[];
     __shared__ int part[256];
     __shared__ int qcnt[kMaxCap / kPiece + 1];
@@ -284,64 +295,68 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
     const int TT = g.T * g.T;
     int* hist = sm;            // per-cell counts
     int* cst = sm + TT;        // per-cell start offsets, then scatter cursors
-    const int4 it = items[blockIdx.x];
-    for (int c = threadIdx.x; c < TT; c += blockDim.x) hist[c] = 0;
-    for (int q = threadIdx.x; q < kMaxCap / kPiece + 1; q += blockDim.x) qcnt[q] = 0;
-    if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
-    __syncthreads();
-    for (int e = threadIdx.x; e < it.z; e += blockDim.x) atomicAdd(&hist[cell_of(loc0[it.y + e], g.T)], 1);
-    __syncthreads();
-    const int seg = (TT + blockDim.x - 1) / blockDim.x;
-    const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
-    int sum = 0;
-    for (int c = c0; c < c1; ++c) sum += hist[c];
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {       // inclusive scan of the 256 partial sums
-        const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+    const int n_items = flags[1];
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {     // uniform across the workgroup
+        const int4 it = items[item];
+        for (int c = threadIdx.x; c < TT; c += blockDim.x) hist[c] = 0;
+        for (int q = threadIdx.x; q < kMaxCap / kPiece + 1; q += blockDim.x) qcnt[q] = 0;
+        if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
         __syncthreads();
-        part[threadIdx.x] += v;
+        for (int e = threadIdx.x; e < it.z; e += blockDim.x) atomicAdd(&hist[cell_of(loc0[it.y + e], g.T)], 1);
         __syncthreads();
-    }
-    int run = part[threadIdx.x] - sum;
-    for (int c = c0; c < c1; ++c) {
-        cst[c] = run;
-        run += hist[c];
-        const int f = hist[c] / kPiece, t = hist[c] % kPiece;
-        for (int q = 0; q < f; ++q) atomicAdd(&qcnt[q], 1);
-        if (t) atomicAdd(&lcnt[t], 1);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {                          // piece slots: full by level, then tails by length
-        int a = 0;
-        for (int q = 0; q < kMaxCap / kPiece + 1; ++q) {
-            const int x = qcnt[q];
-            qcnt[q] = a;
-            a += x;
+        const int seg = (TT + blockDim.x - 1) / blockDim.x;
+        const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
+        int sum = 0;
+        for (int c = c0; c < c1; ++c) sum += hist[c];
+        part[threadIdx.x] = sum;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {       // inclusive scan of the 256 partial sums
+            const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += v;
+            __syncthreads();
         }
-        for (int l = kPiece - 1; l >= 1; --l) {
-            const int x = lcnt[l];
-            lcnt[l] = a;
-            a += x;
+        int run = part[threadIdx.x] - sum;
+        for (int c = c0; c < c1; ++c) {
+            cst[c] = run;
+            run += hist[c];
+            const int f = hist[c] / kPiece, t = hist[c] % kPiece;
+            for (int q = 0; q < f; ++q) atomicAdd(&qcnt[q], 1);
+            if (t) atomicAdd(&lcnt[t], 1);
         }
-        items[blockIdx.x].w = a;
-    }
-    __syncthreads();
-    for (int c = c0; c < c1; ++c) {
-        const int n = hist[c];
-        if (!n) continue;
-        const int f = n / kPiece, t = n % kPiece;
-        const int start = it.y + cst[c];
-        const int lc = ((c / g.T) << 8) | (c % g.T);
-        for (int q = 0; q < f; ++q)
-            pieces[it.y + atomicAdd(&qcnt[q], 1)] = make_int2(start + q * kPiece, kPiece | (lc << 16));
-        if (t) pieces[it.y + atomicAdd(&lcnt[t], 1)] = make_int2(start + f * kPiece, t | (lc << 16));
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
-        const int dst = it.y + atomicAdd(&cst[cell_of(loc0[it.y + e], g.T)], 1);
-        dlt[dst] = dlt0[it.y + e];
-        pos2[it.y + e] = dst;
+        __syncthreads();
+        if (threadIdx.x == 0) {                          // piece slots: full by level, then tails by length
+            int a = 0;
+            for (int q = 0; q < kMaxCap / kPiece + 1; ++q) {
+                const int x = qcnt[q];
+                qcnt[q] = a;
+                a += x;
+            }
+            for (int l = kPiece - 1; l >= 1; --l) {
+                const int x = lcnt[l];
+                lcnt[l] = a;
+                a += x;
+            }
+            items[item].w = a;
+        }
+        __syncthreads();
+        for (int c = c0; c < c1; ++c) {
+            const int n = hist[c];
+            if (!n) continue;
+            const int f = n / kPiece, t = n % kPiece;
+            const int start = it.y + cst[c];
+            const int lc = ((c / g.T) << 8) | (c % g.T);
+            for (int q = 0; q < f; ++q)
+                pieces[it.y + atomicAdd(&qcnt[q], 1)] = make_int2(start + q * kPiece, kPiece | (lc << 16));
+            if (t) pieces[it.y + atomicAdd(&lcnt[t], 1)] = make_int2(start + f * kPiece, t | (lc << 16));
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
+            const int dst = it.y + atomicAdd(&cst[cell_of(loc0[it.y + e], g.T)], 1);
+            dlt[dst] = dlt0[it.y + e];
+            pos2[it.y + e] = dst;
+        }
+        __syncthreads();                                 // LDS counters are reused by the next item
     }
 }
 
@@ -516,7 +531,7 @@ struct UseRegs {
     static constexpr bool value = (sizeof(typename Acc::Reg) == 8) ? (W <= 8) : (W <= 7);
 };
 
-constexpr int kGridWaves = 4;      // waves per gridding workgroup, one private patch each
+constexpr int kGridWaves = 4;      // most waves per gridding workgroup (one private patch each; a.waves at run time)
 
 template <typename Acc, int W>
 __device__ __forceinline__ void flush_piece(typename Acc::Cell* patch, int* owner, int P, int lane, bool have, int l,
@@ -539,9 +554,14 @@ __device__ __forceinline__ void flush_piece(typename Acc::Cell* patch, int* owne
     }
 }
 
+// Persistent: a fixed set of workgroups takes work items from a counter
+// (a.counter, zero at launch) until none are left, so the table is staged
+// once per workgroup and uneven items (many channels of very different
+// sizes) balance dynamically.
 template <typename R, typename Acc, int W>
 __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
     constexpr bool kRegs = UseRegs<Acc, W>::value;
@@ -550,79 +570,84 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
     Cell* patches = reinterpret_cast<Cell*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
-    int* owners = reinterpret_cast<int*>(patches + kGridWaves * P2);
+    const int nw = a.waves;
+    int* owners = reinterpret_cast<int*>(patches + nw * P2);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Cell* patch = patches + wave * P2;
     int* owner = owners + wave * P2;
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
-    for (int i = threadIdx.x; i < kGridWaves * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
-    __syncthreads();
-    const int item = xcd_chunk(blockIdx.x, gridDim.x);
-    const int4 it = a.items[item];
     const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
     const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
     const R dlo = static_cast<R>(a.dlo);
-    constexpr int kB = 4;                                   // entries whose loads are issued together
-    const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
-    for (int rd = 0; rd < rounds; ++rd) {                   // uniform across the workgroup
-        const int p = rd * blockDim.x + threadIdx.x;
-        const bool have = p < it.w;
-        int2 pc = make_int2(0, 0);
-        if (have) pc = a.pieces[it.y + p];
-        const int len = pc.y & 0xffff;
-        const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
-        typename Acc::Reg acc[kRegs ? W * W : 1];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        for (int i = threadIdx.x; i < nw * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= a.n_items) break;                       // uniform across the workgroup
+        const int4 it = a.items[item];
+        constexpr int kB = 4;                               // entries whose loads are issued together
+        const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
+        for (int rd = 0; rd < rounds; ++rd) {               // uniform across the workgroup
+            const int p = rd * blockDim.x + threadIdx.x;
+            const bool have = p < it.w;
+            int2 pc = make_int2(0, 0);
+            if (have) pc = a.pieces[it.y + p];
+            const int len = pc.y & 0xffff;
+            const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
+            typename Acc::Reg acc[kRegs ? W * W : 1];
 #pragma unroll
-        for (int q = 0; q < (kRegs ? W * W : 1); ++q) Acc::zero(acc[q]);
-        for (int j0 = 0; j0 < len; j0 += kB) {
-            VT dv[kB], vv[kB];
+            for (int q = 0; q < (kRegs ? W * W : 1); ++q) Acc::zero(acc[q]);
+            for (int j0 = 0; j0 < len; j0 += kB) {
+                VT dv[kB], vv[kB];
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (j0 + u < len) {
-                    dv[u] = dlt[pc.x + j0 + u];
-                    vv[u] = vis[pc.x + j0 + u];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (j0 + u >= len) break;
-                R cu[W], cv[W];
-                weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
-                weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
-                if constexpr (kRegs) {
-#pragma unroll
-                    for (int r = 0; r < W; ++r) {
-                        const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
-#pragma unroll
-                        for (int c = 0; c < W; ++c) Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                for (int u = 0; u < kB; ++u) {
+                    if (j0 + u < len) {
+                        dv[u] = dlt[pc.x + j0 + u];
+                        vv[u] = vis[pc.x + j0 + u];
                     }
-                } else {
-                    // Wide footprints: flush the visibility tap by tap (one register).
-                    Cell* row = patch + (l >> 8) * P + (l & 255);
+                }
 #pragma unroll
-                    for (int r = 0; r < W; ++r) {
-                        const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+                for (int u = 0; u < kB; ++u) {
+                    if (j0 + u >= len) break;
+                    R cu[W], cv[W];
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                    if constexpr (kRegs) {
 #pragma unroll
-                        for (int c = 0; c < W; ++c) {
-                            typename Acc::Reg one;
-                            Acc::zero(one);
-                            Acc::add(one, ar * cu[c], ai * cu[c]);
-                            Acc::rmw(&row[r * P + c], one);
+                        for (int r = 0; r < W; ++r) {
+                            const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+#pragma unroll
+                            for (int c = 0; c < W; ++c) Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                        }
+                    } else {
+                        // Wide footprints: flush the visibility tap by tap (one register).
+                        Cell* row = patch + (l >> 8) * P + (l & 255);
+#pragma unroll
+                        for (int r = 0; r < W; ++r) {
+                            const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+#pragma unroll
+                            for (int c = 0; c < W; ++c) {
+                                typename Acc::Reg one;
+                                Acc::zero(one);
+                                Acc::add(one, ar * cu[c], ai * cu[c]);
+                                Acc::rmw(&row[r * P + c], one);
+                            }
                         }
                     }
                 }
             }
+            if constexpr (kRegs) flush_piece<Acc, W>(patch, owner, P, lane, have && len > 0, l, acc);
         }
-        if constexpr (kRegs) flush_piece<Acc, W>(patch, owner, P, lane, have && len > 0, l, acc);
-    }
-    __syncthreads();
-    Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(item) * P2;
-    for (int i = threadIdx.x; i < P2; i += blockDim.x) {
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int w = 0; w < kGridWaves; ++w) Acc::merge(re, im, patches[w * P2 + i]);
-        out[i] = Acc::out(re, im);
+        __syncthreads();
+        Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(item) * P2;
+        for (int i = threadIdx.x; i < P2; i += blockDim.x) {
+            double re = 0.0, im = 0.0;
+            for (int w = 0; w < nw; ++w) Acc::merge(re, im, patches[w * P2 + i]);
+            out[i] = Acc::out(re, im);
+        }
+        __syncthreads();                                    // patches and s_item are reused
     }
 }
 
@@ -636,19 +661,25 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
     const int nblk = a.T / kAssembleRows;
-    const int wt = blockIdx.x / nblk;                       // tile within the written window
+    const int per_chan = a.trows * a.tcols;
+    const int chan = blockIdx.x / (nblk * per_chan);
+    const int wt = (blockIdx.x / nblk) % per_chan;          // tile within the written window
     const int rb = (blockIdx.x % nblk) * kAssembleRows;
     const int tm = (a.tr0 + wt / a.tcols) % a.ntx, tn = (a.tc0 + wt % a.tcols) % a.ntx;
-    const int t = tm * a.ntx + tn;
+    const int ntiles = a.ntx * a.ntx;
+    const int cbase = chan * ntiles;                        // global tiles of this channel
+    const int t = cbase + tm * a.ntx + tn;
     const int P = a.T + a.W - 1;
     const int halo = a.W - 1;
     const Cell* patches = reinterpret_cast<const Cell*>(a.patches);
-    VT* grid = reinterpret_cast<VT*>(a.grid);
+    VT* grid = reinterpret_cast<VT*>(a.grid) + static_cast<size_t>(chan) * a.N * a.N;
     int src_t[4], src_dr[4], src_dc[4];
-    src_t[0] = t;                                                        src_dr[0] = 0;   src_dc[0] = 0;
-    src_t[1] = tm * a.ntx + (tn + a.ntx - 1) % a.ntx;                    src_dr[1] = 0;   src_dc[1] = a.T;
-    src_t[2] = ((tm + a.ntx - 1) % a.ntx) * a.ntx + tn;                  src_dr[2] = a.T; src_dc[2] = 0;
-    src_t[3] = ((tm + a.ntx - 1) % a.ntx) * a.ntx + (tn + a.ntx - 1) % a.ntx; src_dr[3] = a.T; src_dc[3] = a.T;
+    src_t[0] = t;                                                                src_dr[0] = 0;   src_dc[0] = 0;
+    src_t[1] = cbase + tm * a.ntx + (tn + a.ntx - 1) % a.ntx;                    src_dr[1] = 0;   src_dc[1] = a.T;
+    src_t[2] = cbase + ((tm + a.ntx - 1) % a.ntx) * a.ntx + tn;                  src_dr[2] = a.T; src_dc[2] = 0;
+    src_t[3] = cbase + ((tm + a.ntx - 1) % a.ntx) * a.ntx + (tn + a.ntx - 1) % a.ntx;
+    src_dr[3] = a.T;
+    src_dc[3] = a.T;
     int i0[4], i1[4];
     for (int s = 0; s < 4; ++s) {
         i0[s] = a.item_start[src_t[s]];
@@ -678,73 +709,90 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
 }
 
 // ---------------------------------------------------------- degridding
+// Persistent like the gridding kernel: workgroups take items from a.counter.
 template <typename R, int W>
 __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_item;
     using VT = typename C2<R>::T;
     constexpr bool kRegs = (sizeof(R) == 4) ? (W <= 8) : (W <= 7);
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
     VT* patch = reinterpret_cast<VT*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
     const int P = a.T + W - 1;
+    const int ntiles = a.ntx * a.ntx;
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
-    const int4 it = a.items[xcd_chunk(blockIdx.x, gridDim.x)];
-    const int tm = it.x / a.ntx, tn = it.x % a.ntx;
-    const VT* grid = reinterpret_cast<const VT*>(a.grid);
-    for (int i = threadIdx.x; i < P * P; i += blockDim.x) {
-        const int r = i / P, c = i - (i / P) * P;
-        const int gr = (tm * a.T + r) & (a.N - 1), gc = (tn * a.T + c) & (a.N - 1);
-        patch[i] = grid[static_cast<size_t>(gr) * a.N + gc];
-    }
-    __syncthreads();
     VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
     const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
     const R dlo = static_cast<R>(a.dlo);
-    constexpr int kB = 4;
-    for (int p = threadIdx.x; p < it.w; p += blockDim.x) {
-        const int2 pc = a.pieces[it.y + p];
-        const int len = pc.y & 0xffff;
-        const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
-        const VT* row = patch + (l >> 8) * P + (l & 255);
-        VT pr[kRegs ? W * W : 1];
-        if constexpr (kRegs) {
-#pragma unroll
-            for (int r = 0; r < W; ++r)
-#pragma unroll
-                for (int c = 0; c < W; ++c) pr[r * W + c] = row[r * P + c];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int item = s_item;
+        if (item >= a.n_items) break;                   // uniform across the workgroup
+        const int4 it = a.items[item];
+        const int chan = it.x / ntiles, lt = it.x % ntiles;
+        const int tm = lt / a.ntx, tn = lt % a.ntx;
+        const VT* grid = reinterpret_cast<const VT*>(a.grid) + static_cast<size_t>(chan) * a.N * a.N;
+        for (int i = threadIdx.x; i < P * P; i += blockDim.x) {
+            const int r = i / P, c = i - (i / P) * P;
+            const int gr = (tm * a.T + r) & (a.N - 1), gc = (tn * a.T + c) & (a.N - 1);
+            patch[i] = grid[static_cast<size_t>(gr) * a.N + gc];
         }
-        for (int j0 = 0; j0 < len; j0 += kB) {
-            VT dv[kB];
+        __syncthreads();
+        constexpr int kB = 4;
+        for (int p = threadIdx.x; p < it.w; p += blockDim.x) {
+            const int2 pc = a.pieces[it.y + p];
+            const int len = pc.y & 0xffff;
+            const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
+            const VT* row = patch + (l >> 8) * P + (l & 255);
+            VT pr[kRegs ? W * W : 1];
+            if constexpr (kRegs) {
 #pragma unroll
-            for (int u = 0; u < kB; ++u)
-                if (j0 + u < len) dv[u] = dlt[pc.x + j0 + u];
+                for (int r = 0; r < W; ++r)
 #pragma unroll
-            for (int u = 0; u < kB; ++u) {
-                if (j0 + u >= len) break;
-                R cu[W], cv[W];
-                weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
-                weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
-                R accr = 0, acci = 0;
+                    for (int c = 0; c < W; ++c) pr[r * W + c] = row[r * P + c];
+            }
+            for (int j0 = 0; j0 < len; j0 += kB) {
+                VT dv[kB];
 #pragma unroll
-                for (int r = 0; r < W; ++r) {
-                    R sr = 0, si = 0;
+                for (int u = 0; u < kB; ++u)
+                    if (j0 + u < len) dv[u] = dlt[pc.x + j0 + u];
 #pragma unroll
-                    for (int c = 0; c < W; ++c) {
-                        const VT gv = kRegs ? pr[r * W + c] : row[r * P + c];
-                        sr += cu[c] * gv.x;
-                        si += cu[c] * gv.y;
+                for (int u = 0; u < kB; ++u) {
+                    if (j0 + u >= len) break;
+                    R cu[W], cv[W];
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                    R accr = 0, acci = 0;
+#pragma unroll
+                    for (int r = 0; r < W; ++r) {
+                        R sr = 0, si = 0;
+#pragma unroll
+                        for (int c = 0; c < W; ++c) {
+                            const VT gv = kRegs ? pr[r * W + c] : row[r * P + c];
+                            sr += cu[c] * gv.x;
+                            si += cu[c] * gv.y;
+                        }
+                        accr += cv[r] * sr;
+                        acci += cv[r] * si;
                     }
-                    accr += cv[r] * sr;
-                    acci += cv[r] * si;
+                    VT o;
+                    o.x = accr;
+                    o.y = acci;
+                    out[pc.x + j0 + u] = o;
                 }
-                VT o;
-                o.x = accr;
-                o.y = acci;
-                out[pc.x + j0 + u] = o;
             }
         }
+        __syncthreads();                                // patch and s_item are reused
     }
+}
+
+// Zero n ints (work counters) with vector stores.
+__global__ void k_zero_ints(int* __restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ FFT
@@ -895,16 +943,32 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
 
 // ------------------------------------------------------------ launchers
 namespace {
+// Workgroups of a persistent launch: as many as the current device's compute
+// units hold at once by LDS (at most 8 per unit). More than fit only wait for
+// a slot and then find the work list drained, so the estimate need not be
+// exact.
+int resident_blocks(size_t shm) {
+    static int cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cus[dev] <= 0) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cus[dev] = n;
+    }
+    const int by_lds = shm > 0 ? static_cast<int>((160 * 1024) / shm) : 8;
+    return cus[dev] * std::max(1, std::min(8, by_lds));
+}
 template <typename R, typename Acc, int W>
 hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
-    const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 4) * dev::kGridWaves;
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>), hipFuncAttributeMaxDynamicSharedMemorySize,
-        160 * 1024);
+    const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 4) * a.waves;
+    const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>);
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(a.n_items), dim3(64 * dev::kGridWaves), shm, s, a);
+    const int nb = std::min(a.n_items, resident_blocks(shm));
+    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(nb), dim3(64 * a.waves), shm, s, a);
     return hipGetLastError();
 }
 template <typename R, int W>
@@ -912,11 +976,11 @@ hipError_t launch_degrid_w(const DegridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
     const size_t shm = tab + static_cast<size_t>(P) * P * sizeof(typename dev::C2<R>::T);
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&dev::k_degrid_items<R, W>), hipFuncAttributeMaxDynamicSharedMemorySize,
-        160 * 1024);
+    const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W>);
+    static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((dev::k_degrid_items<R, W>), dim3(a.n_items), dim3(256), shm, s, a);
+    const int nb = std::min(a.n_items, resident_blocks(shm));
+    hipLaunchKernelGGL((dev::k_degrid_items<R, W>), dim3(nb), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
@@ -942,17 +1006,19 @@ hipError_t dispatch_degrid(const DegridArgs& a, hipStream_t s) {
 }
 }  // namespace
 
-hipError_t launch_plan_count(const double* uv, int64_t nvis, const PlanGeom& g, int* blockhist, int* flags,
-                             hipStream_t s) {
-    const int nb = plan_blocks(nvis);
+hipError_t launch_plan_count(const double* uv, const int4* blocks, int nb, const PlanGeom& g, int* blockhist,
+                             int* flags, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(dev::k_plan_count, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
-                       reinterpret_cast<const double2*>(uv), nvis, g, blockhist, nb, flags);
+                       reinterpret_cast<const double2*>(uv), blocks, nb, g, blockhist, flags);
     return hipGetLastError();
 }
 
-hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, int nb, int* tile_count, hipStream_t s) {
-    hipLaunchKernelGGL(dev::k_plan_colscan, dim3((g.ntiles + 255) / 256), dim3(256), 0, s, g, blockhist, nb, tile_count);
+hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* chan_blocks, int* tile_count,
+                               hipStream_t s) {
+    const int64_t nt = static_cast<int64_t>(g.ntiles) * g.nchan;
+    hipLaunchKernelGGL(dev::k_plan_colscan, dim3(static_cast<unsigned>((nt + 255) / 256)), dim3(256), 0, s, g,
+                       blockhist, chan_blocks, tile_count);
     return hipGetLastError();
 }
 
@@ -963,17 +1029,17 @@ hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_
     return hipGetLastError();
 }
 
-hipError_t launch_plan_scatter(bool f64, const double* uv, int64_t nvis, const PlanGeom& g, const int* tile_start,
-                               const int* blockhist, int* inv, uint16_t* loc0, void* dlt0, hipStream_t s) {
-    const int nb = plan_blocks(nvis);
+hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
+                               const int* tile_start, const int* blockhist, int* inv, uint16_t* loc0, void* dlt0,
+                               hipStream_t s) {
     if (nb == 0) return hipSuccess;
     if (f64)
         hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
-                           reinterpret_cast<const double2*>(uv), nvis, g, tile_start, blockhist, nb, inv, loc0,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, inv, loc0,
                            reinterpret_cast<double2*>(dlt0));
     else
         hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
-                           reinterpret_cast<const double2*>(uv), nvis, g, tile_start, blockhist, nb, inv, loc0,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, inv, loc0,
                            reinterpret_cast<float2*>(dlt0));
     return hipGetLastError();
 }
@@ -983,11 +1049,12 @@ hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_it
                             hipStream_t s) {
     if (max_items == 0) return hipSuccess;
     const size_t shm = 2 * static_cast<size_t>(g.T) * g.T * sizeof(int);
+    const unsigned nb = static_cast<unsigned>(std::min(max_items, 8192));
     if (f64)
-        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(max_items), dim3(256), shm, s, g, items, flags, loc0,
+        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(nb), dim3(256), shm, s, g, items, flags, loc0,
                            reinterpret_cast<const double2*>(dlt0), reinterpret_cast<double2*>(dlt), pos2, pieces);
     else
-        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(max_items), dim3(256), shm, s, g, items, flags, loc0,
+        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(nb), dim3(256), shm, s, g, items, flags, loc0,
                            reinterpret_cast<const float2*>(dlt0), reinterpret_cast<float2*>(dlt), pos2, pieces);
     return hipGetLastError();
 }
@@ -1034,8 +1101,15 @@ hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dev::k_zero_ints, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s) {
-    const unsigned nt = static_cast<unsigned>(a.trows * a.tcols * (a.T / dev::kAssembleRows));
+    const unsigned nt = static_cast<unsigned>(static_cast<int64_t>(a.nchan) * a.trows * a.tcols *
+                                              (a.T / dev::kAssembleRows));
     if (nt == 0) return hipSuccess;
     switch (prec) {
         case LMG_F32: hipLaunchKernelGGL((dev::k_assemble<float, dev::AccF32>), dim3(nt), dim3(256), 0, s, a); break;
@@ -1116,12 +1190,12 @@ hipError_t set_kernel_attributes() {
     return e;
 }
 
-size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms) {
+size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms, int waves) {
     const size_t rs = prec == LMG_F64 ? 8 : 4;
     const size_t cell = prec == LMG_F32 ? 8 : 16;
     const size_t tab = ((static_cast<size_t>(Ms + 1) * W * 4 * rs) + 15) & ~size_t(15);
     const size_t P = static_cast<size_t>(T + W - 1);
-    return tab + P * P * (cell + 4) * dev::kGridWaves;
+    return tab + P * P * (cell + 4) * static_cast<size_t>(waves);
 }
 
 }  // namespace lmg

@@ -135,6 +135,11 @@ def array_16m_case(W: int = 7, with_vis: bool = True, device: str = "cpu") -> Ca
     return array_case(3, 8322, 4096, W, with_vis=with_vis, device=device)
 
 
+def differentiation_case(W: int = 7, with_vis: bool = True, device: str = "cpu") -> Case:
+    """The 16,777,152-visibility tracks on an 8192^2 grid: with x0 = 1/4 the image is 4096^2."""
+    return array_case(3, 8322, 8192, W, with_vis=with_vis, device=device)
+
+
 def channel_counts(seed: int = 5, nchan: int = 256, lo: float = 1e4, hi: float = 2e5) -> np.ndarray:
     """Per-channel visibility counts, log-uniform in [lo, hi]."""
     rng = np.random.default_rng(seed)

@@ -1,0 +1,163 @@
+"""Batched channels: one plan and one launch per kernel over many independent grids.
+
+Each channel is checked against the FP64 oracle run on that channel alone
+(same seeded inputs, the oracle's table), at the parity tolerances (relative
+RMS 1e-12 in FP64, 1e-5 in FP32); the full 256-channel, 1024^2 workload is
+checked on sampled grid cells of a few channels and against the same channels
+gridded one at a time through the single-channel plan.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import imaging as im
+from oracle import lmtable as lt
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_1906_07102_amd as lmg  # noqa: E402
+
+DEV = "cuda:0"
+TOL = {lmg.F32: 1e-5, lmg.F32_KAHAN: 1e-5, lmg.F64: 1e-12}
+_TABLES = {}
+
+
+def tables(W, degree=3, table_size=300, x0=0.25):
+    key = (W, degree, table_size, x0)
+    if key not in _TABLES:
+        otab, h = lt.make_table(W, x0, table_size, degree)
+        _TABLES[key] = (otab, lmg.Table.from_nodes(W, x0, table_size, degree, h, otab.nodes))
+    return _TABLES[key]
+
+
+def rel_rms(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def cdt(prec):
+    return torch.complex128 if prec == lmg.F64 else torch.complex64
+
+
+def dev(x, dtype):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device=DEV, dtype=dtype)
+
+
+def small_batch(seed=21, N=128):
+    """9 channels of uneven size, including an empty one and a single visibility."""
+    rng = np.random.default_rng(seed)
+    counts = np.array([500, 0, 1, 3000, 37, 1200, 64, 2500, 999])
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    n = int(offsets[-1])
+    uv = rng.uniform(-N / 4, N / 4, (n, 2))
+    vis = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    w = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    return uv, vis, w, offsets
+
+
+@pytest.mark.parametrize("prec", [lmg.F32, lmg.F32_KAHAN, lmg.F64])
+@pytest.mark.parametrize("W,tile", [(7, 0), (5, 8), (5, 16), (3, 32)])
+def test_batched_grid_degrid_small(prec, W, tile):
+    print(f"batched small prec={prec} W={W} tile={tile}", flush=True)
+    N = 128
+    uv, vis, w, off = small_batch()
+    otab, gtab = tables(W)
+    plan = lmg.BatchPlan(gtab, N, dev(uv, torch.float64), off, prec, tile)
+    info = plan.info()
+    assert info["channels"] == len(off) - 1
+    if tile:
+        assert info["tile"] == tile
+    G = plan.grid(dev(vis, cdt(prec)), dev(w, torch.float32)).cpu().numpy()
+    rng = np.random.default_rng(5)
+    Gin = rng.standard_normal((len(off) - 1, N, N)) + 1j * rng.standard_normal((len(off) - 1, N, N))
+    V = plan.degrid(dev(Gin, cdt(prec))).cpu().numpy()
+    for c in range(len(off) - 1):
+        a, b = off[c], off[c + 1]
+        ref = im.grid(uv[a:b], vis[a:b], w[a:b].astype(np.float64), N, otab)
+        if b == a:
+            assert np.all(G[c] == 0)
+            continue
+        assert rel_rms(G[c], ref) < TOL[prec], c
+        assert rel_rms(V[a:b], im.degrid(uv[a:b], Gin[c], otab)) < TOL[prec], c
+
+
+def test_batched_one_shot_matches_planned():
+    print("batched one-shot", flush=True)
+    N = 128
+    uv, vis, w, off = small_batch(seed=3)
+    _, gtab = tables(5)
+    uvd, vd, wd = dev(uv, torch.float64), dev(vis, torch.complex128), dev(w, torch.float32)
+    G1 = lmg.grid_batched(gtab, N, uvd, off, vd, wd)
+    plan = lmg.BatchPlan(gtab, N, uvd, off, lmg.F64, 32)
+    G2 = plan.grid(vd, wd)
+    assert rel_rms(G1.cpu().numpy(), G2.cpu().numpy()) < 1e-14
+    V1 = lmg.degrid_batched(gtab, N, uvd, off, G2)
+    V2 = plan.degrid(G2)
+    assert rel_rms(V1.cpu().numpy(), V2.cpu().numpy()) < 1e-14
+
+
+def test_image_calls_reject_batched_plans():
+    N = 128
+    uv, vis, w, off = small_batch(seed=4)
+    _, gtab = tables(5)
+    plan = lmg.BatchPlan(gtab, N, dev(uv, torch.float64), off, lmg.F32)
+    with pytest.raises(lmg.LmgError, match="-5"):
+        plan.make_dirty_image(dev(vis, torch.complex64))
+
+
+# ------------------------------------------- 256 channels on 1024^2 grids ---
+_C5 = {}
+
+
+def c5():
+    if "c" not in _C5:
+        uv, off, _ = synth.multichannel_case()
+        rng = np.random.default_rng(55)
+        vis = (rng.standard_normal(len(uv)) + 1j * rng.standard_normal(len(uv))).astype(np.complex64)
+        _C5["c"] = (uv, off, vis)
+    return _C5["c"]
+
+
+def test_multichannel_full_size_sampled():
+    """256 channels, 1024^2 grids, W = 5, compensated FP32: sampled cells and visibilities vs the oracle."""
+    print("multichannel full size", flush=True)
+    uv, off, vis = c5()
+    N, W = 1024, 5
+    otab, gtab = tables(W)
+    uvd = dev(uv, torch.float64)
+    plan, timings = lmg.autotune_batch(gtab, N, uvd, off, dev(vis, torch.complex64), None, lmg.F32_KAHAN)
+    print(f"autotune timings {timings} -> tile {plan.info()['tile']}", flush=True)
+    assert plan.info()["tile"] in timings
+    G = plan.grid(dev(vis, torch.complex64))
+    Vp = plan.degrid(G)
+    rng = np.random.default_rng(8)
+    for c in rng.choice(len(off) - 1, 4, replace=False):
+        a, b = int(off[c]), int(off[c + 1])
+        cu, cv = im.tap_geometry(uv[a:b, 0], W)[0], im.tap_geometry(uv[a:b, 1], W)[0]
+        k = rng.integers(0, b - a, 200)
+        cells = np.stack([(cv[k] + N // 2 + rng.integers(0, W, 200)) % N,
+                          (cu[k] + N // 2 + rng.integers(0, W, 200)) % N], axis=1)
+        ref = im.grid_cells(uv[a:b], vis[a:b].astype(np.complex128), None, N, otab, cells)
+        got = G[c].cpu().numpy()[cells[:, 0], cells[:, 1]]
+        assert rel_rms(got, ref) < 1e-5, c
+        Gc = G[c].to(torch.complex128).cpu().numpy()
+        sel = rng.integers(a, b, 100)
+        assert rel_rms(Vp.cpu().numpy()[sel], im.degrid(uv[sel], Gc, otab)) < 1e-5, c
+
+
+def test_multichannel_matches_separate_plans():
+    """The batched plan gives each channel what a single-channel plan gives it (same precision)."""
+    print("multichannel vs separate", flush=True)
+    uv, off, vis = c5()
+    N = 1024
+    _, gtab = tables(5)
+    uvd, vd = dev(uv, torch.float64), dev(vis, torch.complex64)
+    plan = lmg.BatchPlan(gtab, N, uvd, off, lmg.F32_KAHAN)
+    G = plan.grid(vd)
+    rng = np.random.default_rng(9)
+    for c in rng.choice(len(off) - 1, 6, replace=False):
+        a, b = int(off[c]), int(off[c + 1])
+        single = lmg.Plan(gtab, N, uvd[a:b].contiguous(), lmg.F32_KAHAN)
+        g1 = single.grid(vd[a:b].contiguous())
+        assert rel_rms(G[c].cpu().numpy(), g1.cpu().numpy()) < 1e-6, c

@@ -108,3 +108,31 @@ def test_size_queries_and_invalid_grids():
     assert lib.lmg_workspace_size(128, 7, 0.25, 10, 3, lmg.OP_GRID, ctypes.byref(n)) == -1
     assert lib.lmg_plan_create(None, 128, 0, 0, None, None, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert lmg.load().lmg_status_string(-2).decode().startswith("workspace")
+
+
+def test_batch_plan_rejects_bad_arguments_before_any_launch():
+    """Argument errors of the batched plan are found on the host (nothing reaches a device)."""
+    lib = lmg.load()
+    import ctypes
+    t = lmg.Table.create(5, 0.25, 300, 3)
+    out = ctypes.c_void_p()
+    I64 = ctypes.c_int64
+
+    def create(offsets, tile=0, N=128, nchan=None):
+        off = (I64 * len(offsets))(*offsets)
+        nc = len(offsets) - 1 if nchan is None else nchan
+        return lib.lmg_batch_plan_create(t.handle, N, lmg.F32, nc, off, None, tile, None, 0, None, ctypes.byref(out))
+
+    assert create([1, 5]) == -1             # offsets[0] != 0
+    assert create([0, 5, 3]) == -1          # decreasing
+    assert create([0, 0], nchan=0) == -1    # no channel
+    assert create([0, 0], tile=24) == -1    # not a power of two
+    assert create([0, 0], tile=4) == -1     # below 8
+    assert create([0, 0], tile=256) == -1   # above N
+    assert create([0, 0], tile=8, N=2048) == -1   # more than 128 x 128 tiles
+    assert create([0, 0]) == -2             # valid arguments, no workspace
+    n = ctypes.c_size_t()
+    assert lib.lmg_batch_workspace_size(1024, 5, 256, 16_000_000, lmg.F32, ctypes.byref(n)) == 0
+    assert n.value > 0
+    assert lib.lmg_batch_workspace_size(1024, 5, 0, 10, lmg.F32, ctypes.byref(n)) == -1
+    assert lib.lmg_workspace_size_batched(1024, 5, 4, 100, lmg.F32, lmg.OP_DIRTY, ctypes.byref(n)) == -1
