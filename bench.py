@@ -191,6 +191,95 @@ def cpu_baseline(case, nvis_sample: int):
     }
 
 
+def _timed(fn, reps, stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def precision_study(lmg, case, uv, vis64, reps=5):
+    """Dirty images of the workload for W = 3, 5, 7 in the three accumulation modes against the direct DFT on
+    the 64 x 64 pixel lattice of tests/golden/dft_samples_16m_4096.txt; with the time of one dirty image +
+    prediction (plan reused). The compensated FP32 mode goes through the autograd wrappers."""
+    import torch
+    d = np.loadtxt(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.txt"))
+    dft = np.zeros((64, 64), dtype=np.complex128)
+    dft[d[:, 0].astype(int), d[:, 1].astype(int)] = d[:, 2] + 1j * d[:, 3]
+    pix = -1024 + 32 * np.arange(64)
+    rows = []
+    for W in (3, 5, 7):
+        table = lmg.Table.create(W, case.x0, case.table_size, case.degree)
+        for name, prec in (("f32", lmg.F32), ("kahan", lmg.F32_KAHAN), ("f64", lmg.F64)):
+            plan = lmg.Plan(table, case.N, uv, prec)
+            vis = vis64.to(torch.complex128) if prec == lmg.F64 else vis64
+            if prec == lmg.F32_KAHAN:
+                run = lambda: lmg.PredictVisibilities.apply(plan, lmg.MakeDirtyImage.apply(plan, vis))
+            else:
+                run = lambda: plan.predict_visibilities(plan.make_dirty_image(vis))
+            img = plan.make_dirty_image(vis)
+            sel = torch.as_tensor(pix + plan.M // 2, device=img.device)
+            smp = img.index_select(0, sel).index_select(1, sel).to(torch.complex128).cpu().numpy()
+            err = float(np.linalg.norm(smp - dft) / np.linalg.norm(dft))
+            ms = _timed(run, reps)
+            rows.append({"W": W, "mode": name, "rel_rms_vs_dft": err, "ms_dirty_plus_predict": round(ms, 4)})
+            print(f"# precision W={W} {name}: err {err:.3e}, {ms:.3f} ms", file=sys.stderr, flush=True)
+            del plan, img
+    t = {(r["W"], r["mode"]): r for r in rows}
+    return {
+        "rows": rows,
+        "speedup_kahan_over_f64_W7": round(t[(7, "f64")]["ms_dirty_plus_predict"] /
+                                           t[(7, "kahan")]["ms_dirty_plus_predict"], 3),
+        "note": "error = relative RMS against the FP64 direct DFT (Eq. 3) on a 64 x 64 pixel lattice; "
+                "time = make_dirty_image + predict_visibilities with the plan reused; the compensated mode "
+                "runs through the autograd wrappers",
+    }
+
+
+def multichannel_study(lmg, reps=5):
+    """256 channels (log-uniform 1e4..2e5 visibilities), 1024^2 grids, W = 5, compensated FP32: gridding +
+    degridding in one batched plan (autotuned tile) against 256 single-channel plans on one stream."""
+    import torch
+    import synth
+    uv_np, off, _ = synth.multichannel_case()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(55)
+    vis = torch.from_numpy((rng.standard_normal(len(uv_np)) + 1j * rng.standard_normal(len(uv_np)))
+                           .astype(np.complex64)).to(dev)
+    uv = torch.from_numpy(uv_np).to(dev)
+    N, W = 1024, 5
+    table = lmg.Table.create(W, 0.25, 300, 3)
+    prec = lmg.F32_KAHAN
+    plan, tune = lmg.autotune_batch(table, N, uv, off, vis, None, prec, tiles=(16, 32, 64))
+    grids = plan.grid(vis)
+    vout = plan.degrid(grids)
+    ms_batched = _timed(lambda: (plan.grid(vis, out=grids), plan.degrid(grids, out=vout)), reps)
+    singles = []
+    for c in range(len(off) - 1):
+        a, b = int(off[c]), int(off[c + 1])
+        singles.append((lmg.Plan(table, N, uv[a:b].contiguous(), prec), vis[a:b].contiguous(), grids[c],
+                        vout[a:b]))
+
+    def separate():
+        for p, v, g, o in singles:
+            p.grid(v, out=g)
+            p.degrid(g, out=o)
+    ms_sep = _timed(separate, max(1, reps // 2))
+    nvis = int(off[-1])
+    return {
+        "workload": "256 channels, 1024^2 grids, W=5, compensated FP32, log-uniform 1e4..2e5 visibilities",
+        "nvis": nvis, "tile": plan.info()["tile"], "autotune_ms": {str(k): round(v, 4) for k, v in tune.items()},
+        "ms_batched_grid_plus_degrid": round(ms_batched, 4), "ms_256_separate": round(ms_sep, 4),
+        "speedup_batched": round(ms_sep / ms_batched, 3), "vis_per_s_batched": nvis / (ms_batched * 1e-3),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -199,6 +288,8 @@ def main():
     ap.add_argument("--precision", choices=["f32", "kahan", "f64"], default="f32")
     ap.add_argument("--workload", choices=["array-16m-4096", "array-1m-2048"], default="array-16m-4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-studies", action="store_true",
+                    help="skip the precision study and the multichannel comparison")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -330,6 +421,13 @@ def main():
         "ms_per_step_plan_reused": round(ms_reuse, 4),
         "source_hash": kernel_source_hash(),
     }
+    if not args.no_studies and args.workload == "array-16m-4096":
+        for key, fn in (("precision_study", lambda: precision_study(lmg, case, uv, vis.to(torch.complex64))),
+                        ("multichannel", lambda: multichannel_study(lmg))):
+            try:
+                out[key] = fn()
+            except Exception as e:          # a study must not cost the main line
+                out[key] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(case, min(args.cpu_sample, nvis))

@@ -48,13 +48,14 @@ struct lmg_plan {
     int4* blocks = nullptr;        // per plan block: (channel, first visibility, count, 0)
     int* chan_blocks = nullptr;    // per channel, its first plan block; nchan + 1 entries
     int4* items = nullptr;
-    int* inv0 = nullptr;           // caller index -> tile-order position (-1: dropped)
-    uint16_t* loc0 = nullptr;      // first-tap cell within the tile, by position
-    void* dlt0 = nullptr;          // offsets, by position
-    void* dlt = nullptr;           // offsets, by entry (cell order within items)
-    int* pos2 = nullptr;           // position -> entry
+    int* inv0 = nullptr;           // caller index -> tile-order position
+    void* off0 = nullptr;          // packed offsets, by tile-order position
+    void* off = nullptr;           // packed offsets, by entry (cell order within items)
+    int* pos2 = nullptr;           // tile-order position -> entry (-1: dropped)
     int* inv = nullptr;            // caller index -> entry (-1: dropped)
     int2* pieces = nullptr;
+    int lb = 0;                    // log2 of the tile edge
+    int F = 0;                     // fraction bits of the packed offsets
     void* coef = nullptr;
     void* twiddle = nullptr;
     void* hpix = nullptr;
@@ -118,8 +119,8 @@ size_t cplx_size(lmg_precision p) { return 2 * real_size(p); }
 size_t patch_cell_size(lmg_precision p) { return p == LMG_F32 ? 8 : 16; }
 
 struct Layout {
-    size_t flags, tile_count, tile_start, item_start, blockhist, blocks, chan_blocks, items, inv0, loc0, dlt0, dlt, pos2,
-        inv, pieces, coef, twiddle, hpix, total;
+    size_t flags, tile_count, tile_start, item_start, blockhist, blocks, chan_blocks, items, inv0, off0, off, pos2, inv, pieces, coef,
+        twiddle, hpix, total;
     int max_items;
     int max_blocks;
 };
@@ -138,17 +139,16 @@ Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap, int nchan =
     size_t o = 0;
     auto take = [&o](size_t bytes) { const size_t at = o; o = align_up(o + bytes); return at; };
     L.flags = take(16 * sizeof(int));
-    L.tile_count = take(tot * sizeof(int));
-    L.tile_start = take((tot + 1) * sizeof(int));
+    L.tile_count = take((tot + 1) * sizeof(int));
+    L.tile_start = take((tot + 2) * sizeof(int));
     L.item_start = take((tot + 1) * sizeof(int));
-    L.blockhist = take(static_cast<size_t>(L.max_blocks) * ntiles * sizeof(int));
+    L.blockhist = take(static_cast<size_t>(L.max_blocks) * (ntiles + 1) * sizeof(int));
     L.blocks = take(static_cast<size_t>(L.max_blocks) * sizeof(int4));
     L.chan_blocks = take((static_cast<size_t>(nchan) + 1) * sizeof(int));
     L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
     L.inv0 = take(static_cast<size_t>(nvis) * sizeof(int));
-    L.loc0 = take(static_cast<size_t>(nvis) * sizeof(uint16_t));
-    L.dlt0 = take(static_cast<size_t>(nvis) * cplx_size(prec));
-    L.dlt = take(static_cast<size_t>(nvis) * cplx_size(prec));
+    L.off0 = take(static_cast<size_t>(nvis) * packed_offset_bytes(prec == LMG_F64));
+    L.off = take(static_cast<size_t>(nvis) * packed_offset_bytes(prec == LMG_F64));
     L.pos2 = take(static_cast<size_t>(nvis) * sizeof(int));
     L.inv = take(static_cast<size_t>(nvis) * sizeof(int));
     L.pieces = take(static_cast<size_t>(nvis) * sizeof(int2));
@@ -280,8 +280,8 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     }
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
-    a.n_items = p->n_items; a.waves = p->waves; a.dlo = delta_low(t->W);
-    a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
+    a.n_items = p->n_items; a.waves = p->waves; a.F = p->F;
+    a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.vis = vs; a.patches = patches; a.counter = counters;
     {
         TraceScope ts("grid_items", s);
@@ -305,8 +305,8 @@ lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* 
     LMG_HIP(launch_zero_ints(counters + 1, 1, s));
     DegridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
-    a.n_items = p->n_items; a.dlo = delta_low(t->W);
-    a.items = p->items; a.pieces = p->pieces; a.dlt = p->dlt; a.coef = p->coef;
+    a.n_items = p->n_items; a.F = p->F;
+    a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
     {
         TraceScope ts("degrid_items", s);
@@ -381,12 +381,14 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     p->chan_blocks = reinterpret_cast<int*>(base + L.chan_blocks);
     p->items = reinterpret_cast<int4*>(base + L.items);
     p->inv0 = reinterpret_cast<int*>(base + L.inv0);
-    p->loc0 = reinterpret_cast<uint16_t*>(base + L.loc0);
-    p->dlt0 = base + L.dlt0;
-    p->dlt = base + L.dlt;
+    p->off0 = base + L.off0;
+    p->off = base + L.off;
     p->pos2 = reinterpret_cast<int*>(base + L.pos2);
     p->inv = reinterpret_cast<int*>(base + L.inv);
     p->pieces = reinterpret_cast<int2*>(base + L.pieces);
+    p->lb = 0;
+    while ((1 << p->lb) < T) ++p->lb;
+    p->F = packed_frac_bits(prec == LMG_F64, p->lb);
     p->coef = base + L.coef;
     p->twiddle = base + L.twiddle;
     p->hpix = base + L.hpix;
@@ -436,12 +438,12 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     {
         TraceScope ts("plan_scatter", s);
         LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, p->blocks, p->nblocks, p->g, p->tile_start, p->blockhist,
-                                    p->inv0, p->loc0, p->dlt0, s));
+                                    delta_low(table->W), p->lb, p->inv0, p->off0, s));
     }
     {
         TraceScope ts("plan_sort_items", s);
-        LMG_HIP(launch_plan_sort(prec == LMG_F64, p->g, p->items, L.max_items, p->flags, p->loc0, p->dlt0, p->dlt,
-                                 p->pos2, p->pieces, s));
+        LMG_HIP(launch_plan_sort(prec == LMG_F64, p->g, p->items, L.max_items, p->flags, static_cast<int>(nvis),
+                                 p->lb, p->off0, p->off, p->pos2, p->pieces, s));
     }
     {
         TraceScope ts("plan_compose", s);

@@ -33,10 +33,10 @@ struct PlanGeom {
 struct GridArgs {
     int N, W, T, ntx, Ms, degree, n_items;
     int waves;             // waves per workgroup, 1..4, each with its own LDS patch
-    double dlo;
+    int F;                 // fraction bits of the packed offsets
     const int4* items;     // (tile, first position, count, pieces)
     const int2* pieces;    // (first entry, length | cell << 16)
-    const void* dlt;       // float2 or double2 offsets, entry order
+    const void* off;       // packed offsets (uint2 or ulonglong2), entry order
     const void* coef;      // coefficient table, float or double
     const void* vis;       // complex, entry order, weights applied
     void* patches;         // n_items patches of (T + W - 1)^2 cells
@@ -53,10 +53,10 @@ struct AssembleArgs {
 
 struct DegridArgs {
     int N, W, T, ntx, Ms, degree, n_items;
-    double dlo;
+    int F;
     const int4* items;
     const int2* pieces;
-    const void* dlt;
+    const void* off;
     const void* coef;
     const void* grid;      // nchan grids of N x N
     void* vis_out;         // entry order
@@ -87,12 +87,14 @@ hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* cha
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
                             int* flags, int cap, hipStream_t s);
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, int* inv, uint16_t* loc0, void* dlt0,
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* off0,
                                hipStream_t s);
-hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
-                            const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
-                            hipStream_t s);
+hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags, int nvis,
+                            int lb, const void* off0, void* off, int* pos2, int2* pieces, hipStream_t s);
 hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s);
+// Bytes of one visibility's packed offsets (both axes).
+size_t packed_offset_bytes(bool f64);
+int packed_frac_bits(bool f64, int lb);
 hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const int* inv, int64_t nvis, void* vs,
                              hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);

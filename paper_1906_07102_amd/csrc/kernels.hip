@@ -45,30 +45,36 @@ __device__ __forceinline__ bool tap_geometry(double u, int W, double ref, int N,
     return true;
 }
 
-// W kernel weights at offset delta from the coefficient table in LDS (App. F).
-template <typename R, int W>
-__device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int degree, R delta, R dlo, R* out) {
-    const R p = (delta - dlo) * static_cast<R>(Ms);
+// W kernel weights from the coefficient table in LDS (App. F) for the
+// packed offset word p (the fixed-point x = delta - delta_lo in its low F + 1
+// bits): the interval k = floor(Ms x) and t = Ms x - k are taken exactly in
+// integers; degree 0 takes the nearest node (ties to the upper one).
+template <typename R, int W, typename P>
+__device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int degree, P p, int F, R* out) {
+    const unsigned long long q = static_cast<unsigned long long>(p) & ((2ull << F) - 1);
+    const unsigned long long m = q * static_cast<unsigned long long>(Ms);
     if (degree == 0) {
-        int k = static_cast<int>(floor(p + static_cast<R>(0.5)));
-        k = min(max(k, 0), Ms);
+        const int k = min(static_cast<int>((m + (1ull << (F - 1))) >> F), Ms);
         const R* c = tab + k * W * 4;
 #pragma unroll
         for (int j = 0; j < W; ++j) out[j] = c[j * 4];
         return;
     }
-    int k = static_cast<int>(floor(p));
-    k = min(max(k, 0), Ms);
-    const R t = p - static_cast<R>(k);
+    const int k = min(static_cast<int>(m >> F), Ms);
+    const unsigned long long r = m - (static_cast<unsigned long long>(k) << F);   // < 2^F
+    R t;
+    if constexpr (sizeof(R) == 4)
+        t = static_cast<float>(static_cast<unsigned>(r)) * __int_as_float((127 - F) << 23);
+    else
+        t = static_cast<double>(r) * __longlong_as_double(static_cast<long long>(1023 - F) << 52);
     const R* c = tab + k * W * 4;
 #pragma unroll
     for (int j = 0; j < W; ++j) {
-        const R* q = c + j * 4;
-        out[j] = q[0] + t * (q[1] + t * (q[2] + t * q[3]));
+        const R* qq = c + j * 4;
+        out[j] = qq[0] + t * (qq[1] + t * (qq[2] + t * qq[3]));
     }
 }
 
-__device__ __forceinline__ int cell_of(int loc, int T) { return (loc >> 8) * T + (loc & 255); }
 
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
 // Streaming kernels map workgroup b to chunk xcd_chunk(b, nb), so that every
@@ -82,15 +88,100 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
 }
 
 // ---------------------------------------------------------------- plan
-// Pass 1: validate coordinates and count visibilities per tile, per plan
-// block (a run of at most kPlanBlockVis visibilities of one channel, kept
-// per block so that pass 3 can place each block's visibilities of a tile in
-// one contiguous run). blocks[b] = (channel, first visibility, count, 0).
+// Packed offsets. A visibility's position in its tile and its fractional
+// offsets are kept, per axis, in one unsigned word (32-bit for the FP32
+// modes, 64-bit for FP64): the first-tap cell within the tile in the top
+// log2(T) bits, and x = delta - delta_lo in [0, 1] as the fixed-point
+// integer q = round(x 2^F) below them. With T = 32 the FP32-mode word keeps
+// x to 2^-26, finer than a float offset near |delta| = 1/2; the FP64 word
+// keeps it to 2^-52.
+template <typename R> struct Pack;
+template <> struct Pack<float> {
+    using T = unsigned int;
+    using T2 = uint2;
+    static constexpr int kBits = 32;
+};
+template <> struct Pack<double> {
+    using T = unsigned long long;
+    using T2 = ulonglong2;
+    static constexpr int kBits = 64;
+};
+// Fraction bits F for tile edge T = 2^lb.
+template <typename R>
+__host__ __device__ __forceinline__ int pack_frac_bits(int lb) {
+    return Pack<R>::kBits == 32 ? 31 - lb : 52;
+}
+
+template <typename R>
+__device__ __forceinline__ typename Pack<R>::T pack_axis(int local_cell, double delta, double dlo, int lb) {
+    using P = typename Pack<R>::T;
+    const int F = pack_frac_bits<R>(lb);
+    const double x = fmin(fmax(delta - dlo, 0.0), 1.0);
+    const P q = static_cast<P>(rint(x * static_cast<double>(1ull << F)));
+    return (static_cast<P>(local_cell) << (F + 1)) | q;
+}
+
+// Wavefront-wide inclusive sum (64 lanes).
+__device__ __forceinline__ int wave_incl_sum(int v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(v, d, 64);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
+
+// Workgroup-wide exclusive sum of one int per thread (blockDim.x a multiple
+// of 64, at most 1024); returns the prefix and the total. `sh` holds 17 ints.
+__device__ __forceinline__ int block_excl_sum(int v, int* sh, int* total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int inc = wave_incl_sum(v);
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int a = 0;
+        for (int i = 0; i < nw; ++i) {
+            const int x = sh[i];
+            sh[i] = a;
+            a += x;
+        }
+        sh[16] = a;
+    }
+    __syncthreads();
+    const int r = sh[wave] + inc - v;
+    *total = sh[16];
+    __syncthreads();
+    return r;
+}
+
+// Workgroup-wide min or max reduction (op 0: min, 1: max, 2: sum).
+__device__ __forceinline__ int block_reduce(int v, int op, int* sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const int o = __shfl_xor(v, d, 64);
+        v = op == 0 ? min(v, o) : op == 1 ? max(v, o) : v + o;
+    }
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    int r = sh[0];
+    for (int i = 1; i < nw; ++i) r = op == 0 ? min(r, sh[i]) : op == 1 ? max(r, sh[i]) : r + sh[i];
+    __syncthreads();
+    return r;
+}
+
+// Pass 1: count visibilities per tile, per plan block (a run of at most
+// kPlanBlockVis visibilities of one channel, kept per block so that pass 3
+// can place each block's visibilities of a tile in one contiguous run). The
+// slot after the tiles counts visibilities whose coordinates are not finite
+// (they are dropped). blocks[b] = (channel, first visibility, count, 0).
 __global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __restrict__ uv, const int4* __restrict__ blocks,
                                                              int nb, PlanGeom g, int* __restrict__ blockhist,
                                                              int* __restrict__ flags) {
     extern __shared__ int hist[];
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) hist[t] = 0;
+    const int hs = g.ntiles + 1;
+    for (int t = threadIdx.x; t < hs; t += blockDim.x) hist[t] = 0;
     __syncthreads();
     const int chunk = xcd_chunk(blockIdx.x, nb);
     const int4 bd = blocks[chunk];
@@ -110,77 +201,97 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_count(const double2* __re
             if (k >= end) break;
             int cu, cv;
             double du, dv;
-            if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv))
+            if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv)) {
                 atomicAdd(&hist[(cv / g.T) * g.ntx + (cu / g.T)], 1);
-            else
+            } else {
+                atomicAdd(&hist[g.ntiles], 1);
                 bad = 1;
+            }
         }
     }
     if (bad) atomicOr(&flags[0], 1);
     __syncthreads();
-    int* row = blockhist + static_cast<size_t>(chunk) * g.ntiles;
-    for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) row[t] = hist[t];
+    int* row = blockhist + static_cast<size_t>(chunk) * hs;
+    for (int t = threadIdx.x; t < hs; t += blockDim.x) row[t] = hist[t];
 }
 
-// Pass 1b: per (channel, tile), the exclusive prefix of the channel's block
-// counts (in place) and the total. Channel c owns blocks
-// [chan_blocks[c], chan_blocks[c + 1]); global tile = c * ntiles + tile.
-__global__ __launch_bounds__(256) void k_plan_colscan(PlanGeom g, int* __restrict__ blockhist,
-                                                      const int* __restrict__ chan_blocks,
-                                                      int* __restrict__ tile_count) {
-    const int64_t gt = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gt >= static_cast<int64_t>(g.ntiles) * g.nchan) return;
-    const int c = static_cast<int>(gt / g.ntiles), t = static_cast<int>(gt % g.ntiles);
+// Pass 1b: per slot (channel c, tile t), the exclusive prefix of the counts of
+// the channel's blocks [chan_blocks[c], chan_blocks[c + 1]) (in place) and
+// their total; slot nchan * ntiles (dropped visibilities) runs over all
+// blocks. Workgroups of kScanGroups x 64 threads: 64 slots, each split into
+// kScanGroups runs of blocks.
+constexpr int kScanGroups = 16;
+__global__ __launch_bounds__(64 * kScanGroups) void k_plan_colscan(PlanGeom g, int* __restrict__ blockhist,
+                                                                   const int* __restrict__ chan_blocks,
+                                                                   int* __restrict__ tile_count) {
+    __shared__ int part[kScanGroups][64];
+    const int64_t tot = static_cast<int64_t>(g.ntiles) * g.nchan;
+    const int hs = g.ntiles + 1;
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * 64 + (threadIdx.x & 63);
+    const int grp = threadIdx.x >> 6;
+    const bool live = slot <= tot;
+    int b0 = 0, b1 = 0, col = 0;
+    if (live) {
+        if (slot == tot) {
+            b0 = 0;
+            b1 = chan_blocks[g.nchan];
+            col = g.ntiles;
+        } else {
+            const int c = static_cast<int>(slot / g.ntiles);
+            b0 = chan_blocks[c];
+            b1 = chan_blocks[c + 1];
+            col = static_cast<int>(slot % g.ntiles);
+        }
+    }
+    const int len = b1 - b0;
+    const int lo = b0 + static_cast<int>((static_cast<int64_t>(len) * grp) / kScanGroups);
+    const int hi = b0 + static_cast<int>((static_cast<int64_t>(len) * (grp + 1)) / kScanGroups);
+    int sum = 0;
+    for (int b = lo; b < hi; ++b) sum += blockhist[static_cast<size_t>(b) * hs + col];
+    part[grp][threadIdx.x & 63] = sum;
+    __syncthreads();
     int run = 0;
-    for (int b = chan_blocks[c]; b < chan_blocks[c + 1]; ++b) {
-        int* p = blockhist + static_cast<size_t>(b) * g.ntiles + t;
+    for (int q = 0; q < grp; ++q) run += part[q][threadIdx.x & 63];
+    for (int b = lo; b < hi; ++b) {
+        int* p = blockhist + static_cast<size_t>(b) * hs + col;
         const int x = *p;
         *p = run;
         run += x;
     }
-    tile_count[gt] = run;
+    if (live && grp == kScanGroups - 1) tile_count[slot] = run;
 }
 
-// Pass 2 (one workgroup): tile offsets, work items, cursors.
+// Pass 2 (one workgroup): slot offsets, work items of at most `cap`
+// visibilities, counts and the occupied band (flags[1] items, [2] valid
+// visibilities, [3] busy tiles, [4..7] min / max occupied tile row and
+// column). tile_start has nslots + 1 entries (the last is nvis).
 __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __restrict__ tile_count,
                                                     int* __restrict__ tile_start, int* __restrict__ item_start,
                                                     int4* __restrict__ items, int* __restrict__ flags, int cap) {
-    __shared__ int part[1024];
-    __shared__ int part2[1024];
-    const int nt = g.ntiles * g.nchan;          // global tiles, channel-major
-    const int per = (nt + blockDim.x - 1) / blockDim.x;
-    const int lo = threadIdx.x * per, hi = min(nt, lo + per);
+    __shared__ int sh[17];
+    const int tot = g.ntiles * g.nchan;          // tile slots, channel-major; slot tot = dropped
+    const int ns = tot + 1;
+    const int per = (ns + blockDim.x - 1) / blockDim.x;
+    const int lo = threadIdx.x * per, hi = min(ns, lo + per);
     int s = 0, si = 0;
     for (int t = lo; t < hi; ++t) {
         s += tile_count[t];
-        si += (tile_count[t] + cap - 1) / cap;
+        if (t < tot) si += (tile_count[t] + cap - 1) / cap;
     }
-    part[threadIdx.x] = s;
-    part2[threadIdx.x] = si;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = 0, b = 0;
-        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) {
-            const int x = part[i], y = part2[i];
-            part[i] = a;
-            part2[i] = b;
-            a += x;
-            b += y;
-        }
-        tile_start[nt] = a;
-        item_start[nt] = b;
-        flags[1] = b;          // number of work items
-        flags[2] = a;          // number of valid visibilities
-    }
-    __syncthreads();
-    s = part[threadIdx.x];
-    si = part2[threadIdx.x];
+    int nvis = 0, nitems = 0;
+    s = block_excl_sum(s, sh, &nvis);
+    si = block_excl_sum(si, sh, &nitems);
     int busy = 0;
-    int rmin = 1 << 30, rmax = -1, cmin = 1 << 30, cmax = -1;   // occupied tile rows and columns
+    int rmin = 1 << 30, rmax = -1, cmin = 1 << 30, cmax = -1;
     for (int t = lo; t < hi; ++t) {
         const int c = tile_count[t];
-        const int ni = (c + cap - 1) / cap;
         tile_start[t] = s;
+        if (t == tot) {                            // dropped visibilities: no items
+            flags[2] = s;
+            s += c;
+            continue;
+        }
+        const int ni = (c + cap - 1) / cap;
         item_start[t] = si;
         if (c > 0) {
             const int lt = t % g.ntiles;
@@ -198,51 +309,40 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
         s += c;
         si += ni;
     }
-    __syncthreads();
-    part[threadIdx.x] = busy;
-    part2[threadIdx.x] = rmin;
-    __syncthreads();
+    busy = block_reduce(busy, 2, sh);
+    rmin = block_reduce(rmin, 0, sh);
+    rmax = block_reduce(rmax, 1, sh);
+    cmin = block_reduce(cmin, 0, sh);
+    cmax = block_reduce(cmax, 1, sh);
     if (threadIdx.x == 0) {
-        int b = 0, m = 1 << 30;
-        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) { b += part[i]; m = min(m, part2[i]); }
-        flags[3] = b;
-        flags[4] = m;
-    }
-    __syncthreads();
-    part[threadIdx.x] = rmax;
-    part2[threadIdx.x] = cmin;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = -1, m = 1 << 30;
-        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) { a = max(a, part[i]); m = min(m, part2[i]); }
-        flags[5] = a;
-        flags[6] = m;
-    }
-    __syncthreads();
-    part[threadIdx.x] = cmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int a = -1;
-        for (int i = 0; i < static_cast<int>(blockDim.x); ++i) a = max(a, part[i]);
-        flags[7] = a;
+        tile_start[ns] = nvis;
+        item_start[tot] = nitems;
+        flags[1] = nitems;
+        flags[3] = busy;
+        flags[4] = rmin;
+        flags[5] = rmax;
+        flags[6] = cmin;
+        flags[7] = cmax;
     }
 }
 
-// Pass 3: give each visibility its tile-order position; store its local
-// first-tap cell and offsets there, and the position under its caller index.
+// Pass 3: give each visibility its tile-order position (inv0, by caller
+// index) and store its packed offsets there (off0).
 template <typename R>
 __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __restrict__ uv,
                                                                const int4* __restrict__ blocks, int nb, PlanGeom g,
                                                                const int* __restrict__ tile_start,
-                                                               const int* __restrict__ blockhist,
-                                                               int* __restrict__ inv, uint16_t* __restrict__ loc0,
-                                                               typename C2<R>::T* __restrict__ dlt0) {
+                                                               const int* __restrict__ blockhist, double dlo, int lb,
+                                                               int* __restrict__ inv0,
+                                                               typename Pack<R>::T2* __restrict__ off0) {
     extern __shared__ int cur[];
+    const int hs = g.ntiles + 1;
     const int chunk = xcd_chunk(blockIdx.x, nb);
     const int4 bd = blocks[chunk];
-    const int* row = blockhist + static_cast<size_t>(chunk) * g.ntiles;
+    const int* row = blockhist + static_cast<size_t>(chunk) * hs;
     const int* ts = tile_start + static_cast<size_t>(bd.x) * g.ntiles;
     for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) cur[t] = ts[t] + row[t];
+    if (threadIdx.x == 0) cur[g.ntiles] = tile_start[static_cast<size_t>(g.ntiles) * g.nchan] + row[g.ntiles];
     __syncthreads();
     const int64_t base = bd.y, end = static_cast<int64_t>(bd.y) + bd.z;
     constexpr int kB = 8;                                    // coordinates loaded together per thread
@@ -261,48 +361,54 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
             double du, dv;
             if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv)) {
                 const int dst = atomicAdd(&cur[(cv / g.T) * g.ntx + (cu / g.T)], 1);
-                inv[k] = dst;
-                loc0[dst] = static_cast<uint16_t>(((cv % g.T) << 8) | (cu % g.T));
-                typename C2<R>::T d;
-                d.x = static_cast<R>(du);
-                d.y = static_cast<R>(dv);
-                dlt0[dst] = d;
+                typename Pack<R>::T2 o;
+                o.x = pack_axis<R>(cu % g.T, du, dlo, lb);
+                o.y = pack_axis<R>(cv % g.T, dv, dlo, lb);
+                off0[dst] = o;
+                inv0[k] = dst;
             } else {
-                inv[k] = -1;                       // dropped: no position
+                inv0[k] = atomicAdd(&cur[g.ntiles], 1);            // dropped: a position after the valid ones
             }
         }
     }
 }
 
 // Pass 4 (workgroups loop over items): order the item's visibilities by
-// footprint cell (counting sort in LDS) and cut each cell's run into pieces
-// of at most kPiece. Full pieces come first, interleaved over cells (all
-// first pieces of every cell, then all second pieces, ...) so that lanes of
-// one wave hold different cells; then the shorter tails, longest first, so
-// that a wave's lanes run loops of similar length. items[i].w receives the
-// number of pieces; the pieces occupy pieces[item start ...].
+// footprint cell (counting sort in LDS) into packed offsets `off` (entry
+// order), with pos2 (tile-order position -> entry), and cut each cell's run
+// into pieces of at most kPiece. Full pieces come first, interleaved over cells (all first
+// pieces of every cell, then all second pieces, ...) so that lanes of one
+// wave hold different cells; then the shorter tails, longest first, so that
+// a wave's lanes run loops of similar length. items[i].w receives the number
+// of pieces; the pieces occupy pieces[item start ...]. Dropped visibilities
+// (tile-order positions n_valid .. nvis) get pos2 = -1.
 template <typename R>
 __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __restrict__ items,
-                                                         const int* __restrict__ flags,
-                                                         const uint16_t* __restrict__ loc0,
-                                                         const typename C2<R>::T* __restrict__ dlt0,
-                                                         typename C2<R>::T* __restrict__ dlt,
+                                                         const int* __restrict__ flags, int nvis, int lb,
+                                                         const typename Pack<R>::T2* __restrict__ off0,
+                                                         typename Pack<R>::T2* __restrict__ off,
                                                          int* __restrict__ pos2, int2* __restrict__ pieces) {
     extern __shared__ int sm[];
     __shared__ int part[256];
     __shared__ int qcnt[kMaxCap / kPiece + 1];
     __shared__ int lcnt[kPiece];
     const int TT = g.T * g.T;
+    const int sh = pack_frac_bits<R>(lb) + 1;         // position of the cell bits
     int* hist = sm;            // per-cell counts
     int* cst = sm + TT;        // per-cell start offsets, then scatter cursors
     const int n_items = flags[1];
+    for (int e = flags[2] + blockIdx.x * blockDim.x + threadIdx.x; e < nvis; e += gridDim.x * blockDim.x)
+        pos2[e] = -1;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {     // uniform across the workgroup
         const int4 it = items[item];
         for (int c = threadIdx.x; c < TT; c += blockDim.x) hist[c] = 0;
         for (int q = threadIdx.x; q < kMaxCap / kPiece + 1; q += blockDim.x) qcnt[q] = 0;
         if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
         __syncthreads();
-        for (int e = threadIdx.x; e < it.z; e += blockDim.x) atomicAdd(&hist[cell_of(loc0[it.y + e], g.T)], 1);
+        for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
+            const typename Pack<R>::T2 r = off0[it.y + e];
+            atomicAdd(&hist[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
+        }
         __syncthreads();
         const int seg = (TT + blockDim.x - 1) / blockDim.x;
         const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
@@ -310,8 +416,8 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
         for (int c = c0; c < c1; ++c) sum += hist[c];
         part[threadIdx.x] = sum;
         __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {       // inclusive scan of the 256 partial sums
-            const int v = (threadIdx.x >= off) ? part[threadIdx.x - off] : 0;
+        for (int o = 1; o < 256; o <<= 1) {            // inclusive scan of the 256 partial sums
+            const int v = (threadIdx.x >= o) ? part[threadIdx.x - o] : 0;
             __syncthreads();
             part[threadIdx.x] += v;
             __syncthreads();
@@ -352,8 +458,9 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
         }
         __syncthreads();
         for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
-            const int dst = it.y + atomicAdd(&cst[cell_of(loc0[it.y + e], g.T)], 1);
-            dlt[dst] = dlt0[it.y + e];
+            const typename Pack<R>::T2 r = off0[it.y + e];
+            const int dst = it.y + atomicAdd(&cst[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
+            off[dst] = r;
             pos2[it.y + e] = dst;
         }
         __syncthreads();                                 // LDS counters are reused by the next item
@@ -361,13 +468,12 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
 }
 
 // Pass 5: caller index -> entry index, composed once so that the per-call
-// permutations need a single lookup: inv[k] = pos2[inv0[k]].
+// permutations need a single lookup: inv[k] = pos2[inv0[k]] (-1: dropped).
 __global__ __launch_bounds__(256) void k_plan_compose(const int* __restrict__ inv0, const int* __restrict__ pos2,
                                                       int64_t nvis, int* __restrict__ inv) {
     const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
-    const int p = inv0[k];
-    inv[k] = p < 0 ? -1 : pos2[p];
+    inv[k] = pos2[inv0[k]];
 }
 
 // Caller order -> entry order: vs[inv[k]] = w_k V_k. Reads are sequential;
@@ -578,8 +684,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
-    const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
-    const R dlo = static_cast<R>(a.dlo);
+    using PT2 = typename Pack<R>::T2;
+    const PT2* off = reinterpret_cast<const PT2*>(a.off);       // packed offsets, entry order
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         for (int i = threadIdx.x; i < nw * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
@@ -600,11 +706,12 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
 #pragma unroll
             for (int q = 0; q < (kRegs ? W * W : 1); ++q) Acc::zero(acc[q]);
             for (int j0 = 0; j0 < len; j0 += kB) {
-                VT dv[kB], vv[kB];
+                PT2 dv[kB];
+                VT vv[kB];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     if (j0 + u < len) {
-                        dv[u] = dlt[pc.x + j0 + u];
+                        dv[u] = off[pc.x + j0 + u];
                         vv[u] = vis[pc.x + j0 + u];
                     }
                 }
@@ -612,8 +719,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
                 for (int u = 0; u < kB; ++u) {
                     if (j0 + u >= len) break;
                     R cu[W], cv[W];
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
                     if constexpr (kRegs) {
 #pragma unroll
                         for (int r = 0; r < W; ++r) {
@@ -724,8 +831,8 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
-    const VT* dlt = reinterpret_cast<const VT*>(a.dlt);
-    const R dlo = static_cast<R>(a.dlo);
+    using PT2 = typename Pack<R>::T2;
+    const PT2* off = reinterpret_cast<const PT2*>(a.off);       // packed offsets, entry order
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -755,16 +862,16 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
                     for (int c = 0; c < W; ++c) pr[r * W + c] = row[r * P + c];
             }
             for (int j0 = 0; j0 < len; j0 += kB) {
-                VT dv[kB];
+                PT2 dv[kB];
 #pragma unroll
                 for (int u = 0; u < kB; ++u)
-                    if (j0 + u < len) dv[u] = dlt[pc.x + j0 + u];
+                    if (j0 + u < len) dv[u] = off[pc.x + j0 + u];
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     if (j0 + u >= len) break;
                     R cu[W], cv[W];
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, dlo, cu);
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, dlo, cv);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
+                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
                     R accr = 0, acci = 0;
 #pragma unroll
                     for (int r = 0; r < W; ++r) {
@@ -1009,16 +1116,16 @@ hipError_t dispatch_degrid(const DegridArgs& a, hipStream_t s) {
 hipError_t launch_plan_count(const double* uv, const int4* blocks, int nb, const PlanGeom& g, int* blockhist,
                              int* flags, hipStream_t s) {
     if (nb == 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::k_plan_count, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
+    hipLaunchKernelGGL(dev::k_plan_count, dim3(nb), dim3(kPlanThreads), (g.ntiles + 1) * sizeof(int), s,
                        reinterpret_cast<const double2*>(uv), blocks, nb, g, blockhist, flags);
     return hipGetLastError();
 }
 
 hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* chan_blocks, int* tile_count,
                                hipStream_t s) {
-    const int64_t nt = static_cast<int64_t>(g.ntiles) * g.nchan;
-    hipLaunchKernelGGL(dev::k_plan_colscan, dim3(static_cast<unsigned>((nt + 255) / 256)), dim3(256), 0, s, g,
-                       blockhist, chan_blocks, tile_count);
+    const int64_t ns = static_cast<int64_t>(g.ntiles) * g.nchan + 1;
+    hipLaunchKernelGGL(dev::k_plan_colscan, dim3(static_cast<unsigned>((ns + 63) / 64)), dim3(64 * dev::kScanGroups),
+                       0, s, g, blockhist, chan_blocks, tile_count);
     return hipGetLastError();
 }
 
@@ -1029,33 +1136,39 @@ hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_
     return hipGetLastError();
 }
 
+size_t packed_offset_bytes(bool f64) { return f64 ? sizeof(dev::Pack<double>::T2) : sizeof(dev::Pack<float>::T2); }
+int packed_frac_bits(bool f64, int lb) {
+    return f64 ? dev::pack_frac_bits<double>(lb) : dev::pack_frac_bits<float>(lb);
+}
+
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, int* inv, uint16_t* loc0, void* dlt0,
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* off0,
                                hipStream_t s) {
     if (nb == 0) return hipSuccess;
+    const size_t shm = (g.ntiles + 1) * sizeof(int);
     if (f64)
-        hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
-                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, inv, loc0,
-                           reinterpret_cast<double2*>(dlt0));
+        hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), shm, s,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
+                           inv0, reinterpret_cast<ulonglong2*>(off0));
     else
-        hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), g.ntiles * sizeof(int), s,
-                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, inv, loc0,
-                           reinterpret_cast<float2*>(dlt0));
+        hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), shm, s,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
+                           inv0, reinterpret_cast<uint2*>(off0));
     return hipGetLastError();
 }
 
-hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags,
-                            const uint16_t* loc0, const void* dlt0, void* dlt, int* pos2, int2* pieces,
-                            hipStream_t s) {
-    if (max_items == 0) return hipSuccess;
+hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags, int nvis,
+                            int lb, const void* off0, void* off, int* pos2, int2* pieces, hipStream_t s) {
     const size_t shm = 2 * static_cast<size_t>(g.T) * g.T * sizeof(int);
-    const unsigned nb = static_cast<unsigned>(std::min(max_items, 8192));
+    const unsigned nb = static_cast<unsigned>(std::max(1, std::min(max_items, 8192)));
     if (f64)
-        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(nb), dim3(256), shm, s, g, items, flags, loc0,
-                           reinterpret_cast<const double2*>(dlt0), reinterpret_cast<double2*>(dlt), pos2, pieces);
+        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(nb), dim3(256), shm, s, g, items, flags, nvis, lb,
+                           reinterpret_cast<const ulonglong2*>(off0), reinterpret_cast<ulonglong2*>(off), pos2,
+                           pieces);
     else
-        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(nb), dim3(256), shm, s, g, items, flags, loc0,
-                           reinterpret_cast<const float2*>(dlt0), reinterpret_cast<float2*>(dlt), pos2, pieces);
+        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(nb), dim3(256), shm, s, g, items, flags, nvis, lb,
+                           reinterpret_cast<const uint2*>(off0), reinterpret_cast<uint2*>(off), pos2,
+                           pieces);
     return hipGetLastError();
 }
 
@@ -1181,9 +1294,9 @@ hipError_t set_kernel_attributes() {
 #define LMG_ATTR(bytes, ...) do { hipError_t r = hipFuncSetAttribute(reinterpret_cast<const void*>(__VA_ARGS__), \
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes); if (r != hipSuccess) e = r; } while (0)
     // Per-tile histograms of up to 128 x 128 ints; the item sort keeps two per-cell arrays of up to 128 x 128.
-    LMG_ATTR(64 * 1024, &dev::k_plan_count);
-    LMG_ATTR(64 * 1024, &dev::k_plan_scatter<float>);
-    LMG_ATTR(64 * 1024, &dev::k_plan_scatter<double>);
+    LMG_ATTR(72 * 1024, &dev::k_plan_count);
+    LMG_ATTR(72 * 1024, &dev::k_plan_scatter<float>);
+    LMG_ATTR(72 * 1024, &dev::k_plan_scatter<double>);
     LMG_ATTR(128 * 1024, &dev::k_plan_sort_items<float>);
     LMG_ATTR(128 * 1024, &dev::k_plan_sort_items<double>);
 #undef LMG_ATTR

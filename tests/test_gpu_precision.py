@@ -9,9 +9,11 @@ FP64 oracle's own error on that lattice, the method error alone, is stored in
 scripts beside them that call only the oracle.
 
 Checks: the FP64 mode reproduces the oracle's error; the error falls with W
-(Sec. 2.2); compensated accumulation is never worse than plain FP32; each
-FP32 mode stays within the FP32 parity tolerance (1e-5 relative) of the
-method error.
+(Sec. 2.2); each FP32 mode stays within the method error plus the rounding
+floor of an FP32 4096^2 transform (24 butterfly stages: about eps sqrt(24),
+bounded here by 5e-7). A second test isolates the accumulation: on the
+16.8M-visibility grid itself, compensated FP32 must be closer to the FP64
+grid than plain FP32, and within the rounding of its complex64 output.
 """
 import os
 
@@ -78,8 +80,27 @@ def test_precision_study():
               f"f64 {err[(W, lmg.F64)]:.3e}", flush=True)
     for W in (3, 5, 7):
         assert abs(err[(W, lmg.F64)] - ref[W]) <= 1e-3 * ref[W] + 1e-12
-        assert err[(W, lmg.F32_KAHAN)] <= err[(W, lmg.F32)] * (1 + 1e-3)
         for prec in (lmg.F32, lmg.F32_KAHAN):
-            assert err[(W, prec)] <= ref[W] + 1e-5
+            assert err[(W, prec)] <= ref[W] + 5e-7
     assert ref[3] > ref[5] > ref[7]
     assert err[(3, lmg.F64)] > err[(5, lmg.F64)] > err[(7, lmg.F64)]
+
+
+def test_compensated_accumulation_on_the_full_grid():
+    """Gridding 16.8M visibilities at W = 7: compensated FP32 against plain FP32, both against FP64."""
+    c, uv, vis64 = case()
+    otab, h = lt.make_table(7, c.x0, 300, 3)
+    tab = lmg.Table.from_nodes(7, c.x0, 300, 3, h, otab.nodes)
+    grids = {}
+    for prec in (lmg.F32, lmg.F32_KAHAN, lmg.F64):
+        print(f"full grid prec={prec}", flush=True)
+        plan = lmg.Plan(tab, c.N, uv, prec)
+        vis = vis64.to(torch.complex128) if prec == lmg.F64 else vis64
+        grids[prec] = plan.grid(vis).to(torch.complex128)
+    ref = grids[lmg.F64]
+    nref = torch.linalg.vector_norm(ref).item()
+    e32 = torch.linalg.vector_norm(grids[lmg.F32] - ref).item() / nref
+    ek = torch.linalg.vector_norm(grids[lmg.F32_KAHAN] - ref).item() / nref
+    print(f"grid rel rms vs FP64: f32 {e32:.3e}  kahan {ek:.3e}", flush=True)
+    assert ek < e32
+    assert ek < 2.0 ** -24          # complex64 rounding of the result (relative RMS below the unit roundoff)
