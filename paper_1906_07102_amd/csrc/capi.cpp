@@ -148,7 +148,7 @@ Layout plan_layout(int N, int64_t nvis, lmg_precision prec, int cap, int nchan =
     L.items = take(static_cast<size_t>(L.max_items) * sizeof(int4));
     L.inv0 = take(static_cast<size_t>(nvis) * sizeof(int));
     L.off0 = take(static_cast<size_t>(nvis) * packed_offset_bytes(prec == LMG_F64));
-    L.off = take(static_cast<size_t>(nvis) * packed_offset_bytes(prec == LMG_F64));
+    L.off = take(static_cast<size_t>(nvis + kRunPad) * packed_offset_bytes(prec == LMG_F64));
     L.pos2 = take(static_cast<size_t>(nvis) * sizeof(int));
     L.inv = take(static_cast<size_t>(nvis) * sizeof(int));
     L.pieces = take(static_cast<size_t>(nvis) * sizeof(int2));
@@ -170,7 +170,7 @@ Scratch scratch_layout(int N, int W, int T, int M, int items, int64_t nvis, lmg_
     const size_t patches = align_up(static_cast<size_t>(items) * P * P * patch_cell_size(prec));
     const size_t grid = align_up(static_cast<size_t>(N) * N * cplx_size(prec));
     const size_t tmp = align_up(static_cast<size_t>(M) * N * cplx_size(prec));
-    const size_t vs = align_up(static_cast<size_t>(nvis) * cplx_size(prec));
+    const size_t vs = align_up(static_cast<size_t>(nvis + kRunPad) * cplx_size(prec));
     Scratch s{};
     size_t o = align_up(kCounters * sizeof(int));
     s.counters = 0;

@@ -17,6 +17,8 @@ constexpr int kPlanBlockVis = 65536;
 inline int plan_blocks(int64_t nvis) { return static_cast<int>((nvis + kPlanBlockVis - 1) / kPlanBlockVis); }
 // Longest run of one footprint cell handled by one lane (a "piece").
 constexpr int kPiece = 32;
+// Elements of padding after the entry-order arrays the item kernels read in runs.
+constexpr int kRunPad = 4;
 // Largest work item (visibilities); bounded by the 16-bit in-item offsets.
 constexpr int kMaxCap = 16384;
 

@@ -509,6 +509,25 @@ __global__ __launch_bounds__(256) void k_permute_out(const typename C2<R>::T* __
     out[k] = v;
 }
 
+// K consecutive elements from p into out. 8-byte elements travel in 16-byte
+// loads (two per load: half the load instructions, and each lane's address
+// touches one line). The arrays read this way are padded by kRunPad elements,
+// so a run that starts inside the array may reach past its last element.
+template <int K, typename T>
+__device__ __forceinline__ void load_run(const T* __restrict__ p, T* out) {
+    if constexpr (sizeof(T) == 8 && K % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < K; i += 2) {
+            uint4 v;
+            __builtin_memcpy(&v, p + i, 16);
+            __builtin_memcpy(&out[i], &v, 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < K; ++i) out[i] = p[i];
+    }
+}
+
 // ------------------------------------------------------------ gridding
 // Accumulation policies. `Reg` accumulates one footprint cell over a piece
 // in registers; `Cell` is the LDS patch element. Patches are private to a
@@ -708,13 +727,8 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
             for (int j0 = 0; j0 < len; j0 += kB) {
                 PT2 dv[kB];
                 VT vv[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    if (j0 + u < len) {
-                        dv[u] = off[pc.x + j0 + u];
-                        vv[u] = vis[pc.x + j0 + u];
-                    }
-                }
+                load_run<kB>(off + pc.x + j0, dv);
+                load_run<kB>(vis + pc.x + j0, vv);
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     if (j0 + u >= len) break;
@@ -863,9 +877,7 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
             }
             for (int j0 = 0; j0 < len; j0 += kB) {
                 PT2 dv[kB];
-#pragma unroll
-                for (int u = 0; u < kB; ++u)
-                    if (j0 + u < len) dv[u] = off[pc.x + j0 + u];
+                load_run<kB>(off + pc.x + j0, dv);
 #pragma unroll
                 for (int u = 0; u < kB; ++u) {
                     if (j0 + u >= len) break;
