@@ -932,6 +932,35 @@ struct FftShape {
     static constexpr int kThreads = (ROWS * N / 4) < 1024 ? (ROWS * N / 4 > 0 ? ROWS * N / 4 : 1) : 1024;
     static constexpr int kB4 = ROWS * N / 4 / kThreads;   // radix-4 butterflies per thread per pass
     static constexpr int kB2 = ROWS * N / 2 / kThreads;
+    static constexpr int kQuarter = N / 4 > 0 ? N / 4 : 1;
+};
+
+// Twiddles: with TW_LDS a quarter-wave table (cos, sin)(2 pi u / N), u < N / 4,
+// is staged in LDS after the rows and the other quadrants follow by symmetry;
+// otherwise they come from the global table (cos, -sin)(2 pi t / N).
+template <typename R, int N, bool TW_LDS>
+__device__ __forceinline__ void twiddle(const typename C2<R>::T* __restrict__ twq, const typename C2<R>::T* __restrict__ tw,
+                                        int t, R& c, R& sn) {
+    if constexpr (TW_LDS) {
+        constexpr int Q = N / 4;
+        const int q = t / Q, u = t - q * Q;
+        const typename C2<R>::T v = twq[u];
+        c = (q == 0) ? v.x : (q == 1) ? -v.y : (q == 2) ? -v.x : v.y;
+        sn = (q == 0) ? v.y : (q == 1) ? v.x : (q == 2) ? -v.y : -v.x;
+    } else {
+        const typename C2<R>::T v = tw[t];
+        c = v.x;
+        sn = -v.y;
+    }
+}
+
+// LDS of one pass: ROWS rows, plus the quarter-wave twiddle table when it fits.
+template <typename R, int N, int ROWS>
+struct FftLds {
+    static constexpr size_t kRows = static_cast<size_t>(ROWS) * N * sizeof(typename C2<R>::T);
+    static constexpr size_t kTw = static_cast<size_t>(FftShape<N, ROWS>::kQuarter) * sizeof(typename C2<R>::T);
+    static constexpr bool kTwLds = N >= 16 && kRows + kTw <= 160 * 1024;
+    static constexpr size_t kBytes = kRows + (kTwLds ? kTw : 0);
 };
 
 template <typename R, int N, int ROWS>
@@ -939,9 +968,13 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
     extern __shared__ __align__(16) unsigned char smem[];
     using VT = typename C2<R>::T;
     using S = FftShape<N, ROWS>;
+    constexpr bool kTwLds = FftLds<R, N, ROWS>::kTwLds;
     constexpr int NT = S::kThreads;
     VT* buf = reinterpret_cast<VT*>(smem);
-    const int row0 = blockIdx.x * ROWS;
+    VT* twq = buf + ROWS * N;
+    // Consecutive row blocks go to one XCD, so that its L2 gathers the narrow transposed writes of
+    // neighbouring blocks into whole lines.
+    const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * ROWS;
     const VT* src = reinterpret_cast<const VT*>(a.src);
     const VT* tw = reinterpret_cast<const VT*>(a.twiddle);   // (cos, -sin)(2 pi t / N)
     const R* h_in = reinterpret_cast<const R*>(a.h_in);
@@ -964,6 +997,13 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
         }
         buf[rr * N + s] = v;
     }
+    if constexpr (kTwLds) {
+        for (int u = threadIdx.x; u < N / 4; u += NT) {
+            VT t = reinterpret_cast<const VT*>(a.twiddle)[u];
+            t.y = -t.y;
+            twq[u] = t;
+        }
+    }
     __syncthreads();
     const R sg = static_cast<R>(a.sign);
     int Ns = 1;
@@ -982,8 +1022,9 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
             for (int r = 0; r < 4; ++r) {
                 VT x = buf[rr * N + j + r * nb];
                 if (r) {
-                    const VT t = tw[(r * jm * stride) & (N - 1)];
-                    const R c = t.x, sn = -sg * t.y;        // e^{sign i 2 pi r jm / (4 Ns)}
+                    R c, sn;
+                    twiddle<R, N, kTwLds>(twq, tw, (r * jm * stride) & (N - 1), c, sn);
+                    sn *= sg;                                  // e^{sign i 2 pi r jm / (4 Ns)}
                     const R xr = x.x * c - x.y * sn;
                     x.y = x.x * sn + x.y * c;
                     x.x = xr;
@@ -1024,8 +1065,9 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
             const int jm = j % Ns;
             const VT x0 = buf[rr * N + j];
             VT x = buf[rr * N + j + nb];
-            const VT t = tw[(jm * stride) & (N - 1)];
-            const R c = t.x, sn = -sg * t.y;
+            R c, sn;
+            twiddle<R, N, kTwLds>(twq, tw, (jm * stride) & (N - 1), c, sn);
+            sn *= sg;
             const R xr = x.x * c - x.y * sn;
             x.y = x.x * sn + x.y * c;
             x.x = xr;
@@ -1266,7 +1308,7 @@ hipError_t launch_fft_nr(const FftArgs& a, hipStream_t s) {
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (attr != hipSuccess) return attr;
     const unsigned nb = static_cast<unsigned>((a.nrows + ROWS - 1) / ROWS);
-    const size_t shm = static_cast<size_t>(ROWS) * N * sizeof(typename dev::C2<R>::T);
+    const size_t shm = dev::FftLds<R, N, ROWS>::kBytes;
     hipLaunchKernelGGL((dev::k_fft_pass<R, N, ROWS>), dim3(nb), dim3(S::kThreads), shm, s, a);
     return hipGetLastError();
 }
