@@ -831,12 +831,20 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
 
 // ---------------------------------------------------------- degridding
 // Persistent like the gridding kernel: workgroups take items from a.counter.
+// The item's (T+W-1)^2 patch of the grid is staged in LDS; then each lane
+// takes one visibility, in entry order, so loads of the packed offsets and
+// stores of the results are contiguous across the wave. Entries are sorted
+// by footprint cell, so lanes of a wave mostly share a cell and read the
+// same patch addresses (an LDS broadcast). The cell comes from the packed
+// offset word (bits above F). (Caching a lane's footprint in registers over
+// a run of its visibilities measured slower: the register cost lowers
+// occupancy more than the LDS reads it saves.)
 template <typename R, int W>
 __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
     using VT = typename C2<R>::T;
-    constexpr bool kRegs = (sizeof(R) == 4) ? (W <= 8) : (W <= 7);
+    using PT2 = typename Pack<R>::T2;
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
     VT* patch = reinterpret_cast<VT*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
@@ -845,8 +853,8 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
-    using PT2 = typename Pack<R>::T2;
-    const PT2* off = reinterpret_cast<const PT2*>(a.off);       // packed offsets, entry order
+    const PT2* off = reinterpret_cast<const PT2*>(a.off);
+    const int cshift = a.F + 1;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
@@ -862,47 +870,30 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
             patch[i] = grid[static_cast<size_t>(gr) * a.N + gc];
         }
         __syncthreads();
-        constexpr int kB = 4;
-        for (int p = threadIdx.x; p < it.w; p += blockDim.x) {
-            const int2 pc = a.pieces[it.y + p];
-            const int len = pc.y & 0xffff;
-            const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
-            const VT* row = patch + (l >> 8) * P + (l & 255);
-            VT pr[kRegs ? W * W : 1];
-            if constexpr (kRegs) {
+        for (int e = it.y + threadIdx.x; e < it.y + it.z; e += blockDim.x) {
+            const PT2 d = off[e];
+            const int cu = static_cast<int>(d.x >> cshift), cv = static_cast<int>(d.y >> cshift);
+            R wu[W], wv[W];
+            weights<R, W>(tab, a.Ms, a.degree, d.x, a.F, wu);
+            weights<R, W>(tab, a.Ms, a.degree, d.y, a.F, wv);
+            const VT* row = patch + cv * P + cu;
+            R accr = 0, acci = 0;
 #pragma unroll
-                for (int r = 0; r < W; ++r)
+            for (int r = 0; r < W; ++r) {
+                R sr = 0, si = 0;
 #pragma unroll
-                    for (int c = 0; c < W; ++c) pr[r * W + c] = row[r * P + c];
-            }
-            for (int j0 = 0; j0 < len; j0 += kB) {
-                PT2 dv[kB];
-                load_run<kB>(off + pc.x + j0, dv);
-#pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    if (j0 + u >= len) break;
-                    R cu[W], cv[W];
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
-                    R accr = 0, acci = 0;
-#pragma unroll
-                    for (int r = 0; r < W; ++r) {
-                        R sr = 0, si = 0;
-#pragma unroll
-                        for (int c = 0; c < W; ++c) {
-                            const VT gv = kRegs ? pr[r * W + c] : row[r * P + c];
-                            sr += cu[c] * gv.x;
-                            si += cu[c] * gv.y;
-                        }
-                        accr += cv[r] * sr;
-                        acci += cv[r] * si;
-                    }
-                    VT o;
-                    o.x = accr;
-                    o.y = acci;
-                    out[pc.x + j0 + u] = o;
+                for (int c = 0; c < W; ++c) {
+                    const VT gv = row[r * P + c];
+                    sr += wu[c] * gv.x;
+                    si += wu[c] * gv.y;
                 }
+                accr += wv[r] * sr;
+                acci += wv[r] * si;
             }
+            VT o;
+            o.x = accr;
+            o.y = acci;
+            out[e] = o;
         }
         __syncthreads();                                // patch and s_item are reused
     }
