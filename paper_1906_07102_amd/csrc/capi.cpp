@@ -104,10 +104,23 @@ int fit_tile(int T, int N, lmg_precision prec, int W, int Ms) {
     while (T > 8 && grid_lds_bytes(prec, W, T, Ms, kMaxGridWaves) > kMaxDynLds && N / (T / 2) <= 128) T /= 2;
     return T;
 }
+// Waves (private patches) per gridding workgroup: the count that lets a
+// compute unit hold the most waves by LDS (160 KB per unit), capped at what
+// the kernel's registers allow (env LMG_GRID_WAVES overrides, 1..4).
 int fit_waves(int T, lmg_precision prec, int W, int Ms) {
-    int waves = kMaxGridWaves;
-    while (waves > 1 && grid_lds_bytes(prec, W, T, Ms, waves) > kMaxDynLds) --waves;
-    return waves;
+    const int forced = env_int("LMG_GRID_WAVES", 0);
+    if (forced >= 1 && forced <= kMaxGridWaves && grid_lds_bytes(prec, W, T, Ms, forced) <= kMaxDynLds) return forced;
+    // Waves per compute unit the kernel's registers allow: about 3 per SIMD for plain FP32 (W x W
+    // complex accumulators), 1 for the compensated and FP64 forms (twice the accumulator registers).
+    const int by_registers = prec == LMG_F32 ? 12 : 4;
+    int best = 1, best_total = 0;
+    for (int w = 1; w <= kMaxGridWaves; ++w) {
+        const size_t b = grid_lds_bytes(prec, W, T, Ms, w) + 256;
+        if (b > kMaxLds) break;
+        const int total = std::min(static_cast<int>(kMaxLds / b) * w, by_registers);
+        if (total > best_total) { best = w; best_total = total; }
+    }
+    return best;
 }
 
 int choose_cap() { return std::min(env_int("LMG_CAP", 8192), kMaxCap); }

@@ -649,31 +649,45 @@ struct AccF64 {
     __device__ static Cell out(double re, double im) { return make_double2(re, im); }
 };
 
-// Register accumulation needs W*W accumulators per lane; beyond these widths
-// a piece is flushed after every visibility.
+// Register accumulation: a lane sums one piece's contributions to a group of
+// RG footprint rows (RG x W accumulators) and then adds them to the patch;
+// wider footprints, or the two-register-per-value compensated and FP64
+// accumulators, take several such passes over the piece so that the
+// accumulators stay within about kAccRegs registers (more waves fit).
+constexpr int kAccRegs = 112;
 template <typename Acc, int W>
-struct UseRegs {
-    static constexpr bool value = (sizeof(typename Acc::Reg) == 8) ? (W <= 8) : (W <= 7);
+struct RowGroup {
+    static constexpr int kRegsPerTap = static_cast<int>(sizeof(typename Acc::Reg) / 4);
+    static constexpr int kRG0 = kAccRegs / (kRegsPerTap * W);
+    static constexpr int RG = kRG0 < 1 ? 1 : (kRG0 > W ? W : kRG0);
+    static constexpr int kPasses = (W + RG - 1) / RG;
 };
 
 constexpr int kGridWaves = 4;      // most waves per gridding workgroup (one private patch each; a.waves at run time)
 
-template <typename Acc, int W>
-__device__ __forceinline__ void flush_piece(typename Acc::Cell* patch, int* owner, int P, int lane, bool have, int l,
-                                            const typename Acc::Reg* acc) {
-    // Lanes holding the same cell take turns: each round one of them wins
-    // the cell (the last store to its owner word) and adds its W x W values.
+// Add the piece's accumulated rows r0 .. r0 + RG - 1 (those below W) to the
+// patch. Lanes holding the same cell take turns: each round one of them wins
+// the cell (the last store to its owner byte) and adds its values.
+template <typename Acc, int W, int RG>
+__device__ __forceinline__ void flush_rows(typename Acc::Cell* patch, unsigned char* owner, int P, int lane, bool have,
+                                           int l, int r0, const typename Acc::Reg* acc) {
     bool pending = have;
     const int cidx = (l >> 8) * P + (l & 255);
     while (__any(pending)) {
-        if (pending) __hip_atomic_store(&owner[cidx], lane, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        const int who = pending ? __hip_atomic_load(&owner[cidx], __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WAVEFRONT) : -1;
+        if (pending)
+            __hip_atomic_store(&owner[cidx], static_cast<unsigned char>(lane), __ATOMIC_SEQ_CST,
+                               __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int who = pending ? static_cast<int>(__hip_atomic_load(&owner[cidx], __ATOMIC_SEQ_CST,
+                                                                     __HIP_MEMORY_SCOPE_WAVEFRONT))
+                                : -1;
         if (pending && who == lane) {
-            typename Acc::Cell* row = patch + cidx;
+            typename Acc::Cell* row = patch + cidx + r0 * P;
 #pragma unroll
-            for (int r = 0; r < W; ++r)
+            for (int r = 0; r < RG; ++r) {
+                if (r0 + r >= W) break;
 #pragma unroll
-                for (int c = 0; c < W; ++c) Acc::rmw(&row[r * P + c], acc[UseRegs<Acc, W>::value ? r * W + c : 0]);
+                for (int c = 0; c < W; ++c) Acc::rmw(&row[r * P + c], acc[r * W + c]);
+            }
             pending = false;
         }
     }
@@ -688,23 +702,24 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
     using VT = typename C2<R>::T;
+    using PT2 = typename Pack<R>::T2;
     using Cell = typename Acc::Cell;
-    constexpr bool kRegs = UseRegs<Acc, W>::value;
+    constexpr int RG = RowGroup<Acc, W>::RG;
+    constexpr int NPASS = RowGroup<Acc, W>::kPasses;
     const int P = a.T + W - 1;
     const int P2 = P * P;
     R* tab = reinterpret_cast<R*>(smem);
     const int ntab = (a.Ms + 1) * W * 4;
     Cell* patches = reinterpret_cast<Cell*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
     const int nw = a.waves;
-    int* owners = reinterpret_cast<int*>(patches + nw * P2);
+    unsigned char* owners = reinterpret_cast<unsigned char*>(patches + nw * P2);   // a lane id per cell
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     Cell* patch = patches + wave * P2;
-    int* owner = owners + wave * P2;
+    unsigned char* owner = owners + wave * P2;
     const R* gtab = reinterpret_cast<const R*>(a.coef);
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
-    using PT2 = typename Pack<R>::T2;
-    const PT2* off = reinterpret_cast<const PT2*>(a.off);       // packed offsets, entry order
+    const PT2* off = reinterpret_cast<const PT2*>(a.off);   // packed offsets, entry order
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         for (int i = threadIdx.x; i < nw * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
@@ -721,45 +736,34 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
             if (have) pc = a.pieces[it.y + p];
             const int len = pc.y & 0xffff;
             const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
-            typename Acc::Reg acc[kRegs ? W * W : 1];
 #pragma unroll
-            for (int q = 0; q < (kRegs ? W * W : 1); ++q) Acc::zero(acc[q]);
-            for (int j0 = 0; j0 < len; j0 += kB) {
-                PT2 dv[kB];
-                VT vv[kB];
-                load_run<kB>(off + pc.x + j0, dv);
-                load_run<kB>(vis + pc.x + j0, vv);
+            for (int pass = 0; pass < NPASS; ++pass) {
+                const int r0 = pass * RG;
+                typename Acc::Reg acc[RG * W];
 #pragma unroll
-                for (int u = 0; u < kB; ++u) {
-                    if (j0 + u >= len) break;
-                    R cu[W], cv[W];
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
-                    weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
-                    if constexpr (kRegs) {
+                for (int q = 0; q < RG * W; ++q) Acc::zero(acc[q]);
+                for (int j0 = 0; j0 < len; j0 += kB) {
+                    PT2 dv[kB];
+                    VT vv[kB];
+                    load_run<kB>(off + pc.x + j0, dv);
+                    load_run<kB>(vis + pc.x + j0, vv);
 #pragma unroll
-                        for (int r = 0; r < W; ++r) {
-                            const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
+                    for (int u = 0; u < kB; ++u) {
+                        if (j0 + u >= len) break;
+                        R cu[W], cv[W];
+                        weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
+                        weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
+#pragma unroll
+                        for (int r = 0; r < RG; ++r) {
+                            if (r0 + r >= W) break;
+                            const R ar = vv[u].x * cv[r0 + r], ai = vv[u].y * cv[r0 + r];
 #pragma unroll
                             for (int c = 0; c < W; ++c) Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
                         }
-                    } else {
-                        // Wide footprints: flush the visibility tap by tap (one register).
-                        Cell* row = patch + (l >> 8) * P + (l & 255);
-#pragma unroll
-                        for (int r = 0; r < W; ++r) {
-                            const R ar = vv[u].x * cv[r], ai = vv[u].y * cv[r];
-#pragma unroll
-                            for (int c = 0; c < W; ++c) {
-                                typename Acc::Reg one;
-                                Acc::zero(one);
-                                Acc::add(one, ar * cu[c], ai * cu[c]);
-                                Acc::rmw(&row[r * P + c], one);
-                            }
-                        }
                     }
                 }
+                flush_rows<Acc, W, RG>(patch, owner, P, lane, have && len > 0, l, r0, acc);
             }
-            if constexpr (kRegs) flush_piece<Acc, W>(patch, owner, P, lane, have && len > 0, l, acc);
         }
         __syncthreads();
         Cell* out = reinterpret_cast<Cell*>(a.patches) + static_cast<size_t>(item) * P2;
@@ -1115,7 +1119,7 @@ template <typename R, typename Acc, int W>
 hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
-    const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 4) * a.waves;
+    const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 1) * a.waves;
     const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
@@ -1353,7 +1357,7 @@ size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms, int waves) {
     const size_t cell = prec == LMG_F32 ? 8 : 16;
     const size_t tab = ((static_cast<size_t>(Ms + 1) * W * 4 * rs) + 15) & ~size_t(15);
     const size_t P = static_cast<size_t>(T + W - 1);
-    return tab + P * P * (cell + 4) * static_cast<size_t>(waves);
+    return tab + P * P * (cell + 1) * static_cast<size_t>(waves);
 }
 
 }  // namespace lmg
