@@ -105,7 +105,6 @@ hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s);
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s);
 hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s);
 hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s);
-int fft_rows_per_block(int N, bool f64);
 hipError_t set_kernel_attributes();
 // LDS bytes of the gridding kernel with `waves` private patches (the
 // degridding kernel needs no more than one patch).

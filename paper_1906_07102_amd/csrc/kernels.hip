@@ -1288,13 +1288,6 @@ hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s)
     return prec == LMG_F64 ? dispatch_degrid<double>(a, s) : dispatch_degrid<float>(a, s);
 }
 
-int fft_rows_per_block(int N, bool f64) {
-    const size_t row_bytes = static_cast<size_t>(N) * (f64 ? 16 : 8);
-    int rows = 4;
-    while (rows > 1 && rows * row_bytes > 131072) rows /= 2;
-    return rows;
-}
-
 namespace {
 template <typename R, int N, int ROWS>
 hipError_t launch_fft_nr(const FftArgs& a, hipStream_t s) {
