@@ -129,9 +129,15 @@ void lmg_table_destroy(lmg_table* t);
  *
  * N: power of two in [max(64, 2W), 8192]; x0 * N * 2 an integer (taken
  * from the table). nvis >= 0. uv: device (nvis, 2) float64.
- * lmg_plan_create synchronizes `stream` once, to size the work lists; it
- * leaves LMG_EDATA to be reported by lmg_plan_check when a coordinate is NaN
- * or infinite (such visibilities are dropped from every later call).
+ * lmg_plan_create only enqueues work on `stream`: the plan's counts (work
+ * items, occupied band, dropped visibilities) come back asynchronously and
+ * the host waits for them only where it needs them (lmg_plan_check,
+ * lmg_plan_info, and the transforms of the image calls, after the gridding
+ * kernels are queued). Planned calls on any stream wait on the device for
+ * the plan's kernels. Visibilities with a NaN or infinite coordinate are
+ * dropped from every later call and reported as LMG_EDATA by lmg_plan_check.
+ * A plan may be used by several host threads; its calls must not overlap
+ * with lmg_plan_destroy.
  */
 typedef struct lmg_plan lmg_plan;
 
@@ -139,13 +145,16 @@ lmg_status lmg_plan_workspace_size(int N, int W, int64_t nvis, lmg_precision pre
 lmg_status lmg_plan_create(const lmg_table* table, int N, lmg_precision prec, int64_t nvis,
                            const double* uv, void* workspace, size_t ws_bytes, void* stream,
                            lmg_plan** out);
-/* LMG_OK, or LMG_EDATA if non-finite coordinates were dropped. Host query. */
+/* LMG_OK, or LMG_EDATA if non-finite coordinates were dropped. Host query
+ * (waits for the plan's kernels). */
 lmg_status lmg_plan_check(const lmg_plan* p);
-/* Tile edge, number of work items and occupied tiles (any pointer may be NULL). */
+/* Tile edge, number of work items and occupied tiles (any pointer may be
+ * NULL). Waits for the plan's kernels. */
 lmg_status lmg_plan_info(const lmg_plan* p, int* tile, int* n_items, int* n_busy_tiles, int64_t* n_valid);
 void lmg_plan_destroy(lmg_plan* p);
 
-/* Scratch a planned call needs beyond its inputs and outputs (device bytes). */
+/* Scratch a planned call needs beyond its inputs and outputs (device bytes),
+ * sized for the most work items the plan can have (known without waiting). */
 lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes);
 #define LMG_OP_GRID 0
 #define LMG_OP_DEGRID 1
@@ -181,7 +190,8 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
 /* ------------------------------------------------ one-shot (unplanned) calls
  * Build a plan inside `workspace`, run the call, and release the plan. The
  * workspace size comes from lmg_workspace_size for the same (N, W, nvis,
- * prec, op). These synchronize `stream` once (plan sizing). */
+ * prec, op). They return after the plan's kernels have finished (the plan is
+ * released), so they may block the host. */
 lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes);
 lmg_status lmg_grid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
                     const void* vis, const float* w, void* grid, void* workspace, size_t ws_bytes, void* stream);
@@ -217,7 +227,8 @@ lmg_status lmg_batch_plan_create(const lmg_table* table, int N, lmg_precision pr
 lmg_status lmg_batch_info(const lmg_plan* p, int* nchan, int* tile, int* waves);
 
 /* One-shot batched gridding (overwrites all nchan grids) and degridding; op is
- * LMG_OP_GRID or LMG_OP_DEGRID. These synchronize `stream` once. */
+ * LMG_OP_GRID or LMG_OP_DEGRID. They return after the plan's kernels have
+ * finished (the plan is released), so they may block the host. */
 lmg_status lmg_workspace_size_batched(int N, int W, int nchan, int64_t nvis, lmg_precision prec, int op,
                                       size_t* bytes);
 lmg_status lmg_grid_batched(const lmg_table* t, int N, lmg_precision prec, int nchan, const int64_t* offsets,

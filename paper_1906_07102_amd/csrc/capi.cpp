@@ -26,20 +26,26 @@ struct lmg_plan {
     lmg_precision prec = LMG_F32;
     PlanGeom g{};
     int64_t nvis = 0;
-    int64_t n_valid = 0;
-    int n_items = 0;
-    int n_busy = 0;
+    // Counts the plan kernels leave in flags[]; read back asynchronously into
+    // host_flags and parsed on the first host query (ensure_flags).
+    mutable int64_t n_valid = 0;
+    mutable int n_items = 0;
+    mutable int n_busy = 0;
+    mutable bool flags_read = false;
+    mutable std::mutex flags_mu;
+    int* host_flags = nullptr;     // pinned slot of 8 ints
+    hipEvent_t ready = nullptr;    // recorded after the plan's last kernel and the readback
     int max_items = 0;
     int cap = 0;
     int M = 0;                  // retained image size 2 x0 N
     int waves = 0;              // waves (private LDS patches) per gridding workgroup
     int nchan = 1;              // channels (grids), each with its own run of visibilities
     int nblocks = 0;            // plan blocks (runs of <= kPlanBlockVis visibilities of one channel)
-    bool bad_data = false;
+    mutable bool bad_data = false;
     // Occupied band of the grid (storage rows / columns [lo, hi)) and the
     // window of tiles that covers it (first tile, number of tiles).
-    int band_r0 = 0, band_r1 = 0, band_c0 = 0, band_c1 = 0;
-    int win_r0 = 0, win_rn = 0, win_c0 = 0, win_cn = 0;
+    mutable int band_r0 = 0, band_r1 = 0, band_c0 = 0, band_c1 = 0;
+    mutable int win_r0 = 0, win_rn = 0, win_c0 = 0, win_cn = 0;
     int* flags = nullptr;
     int* tile_count = nullptr;
     int* tile_start = nullptr;
@@ -59,6 +65,7 @@ struct lmg_plan {
     void* coef = nullptr;
     void* twiddle = nullptr;
     void* hpix = nullptr;
+    ~lmg_plan();
 };
 
 namespace {
@@ -254,6 +261,111 @@ lmg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     return LMG_OK;
 }
 
+// The plan constants of (table, N, precision) in pinned host memory, built on
+// first use: copies from it are asynchronous. nullptr if pinned memory is
+// unavailable (the caller then uploads from pageable memory).
+const lmg_table::Pinned* pinned_constants(const lmg_table* t, int N, lmg_precision prec, const std::vector<double>& h) {
+    std::lock_guard<std::mutex> lk(t->cache_mu);
+    const auto key = std::make_pair(N, static_cast<int>(prec));
+    auto it = t->pinned.find(key);
+    if (it != t->pinned.end()) return it->second.host ? &it->second : nullptr;
+    lmg_table::Pinned pc;
+    const bool f64 = prec == LMG_F64;
+    pc.coef_bytes = f64 ? t->coef64.size() * 8 : t->coef32.size() * 4;
+    pc.twiddle_bytes = 2 * static_cast<size_t>(N) * (f64 ? 8 : 4);
+    pc.hpix_bytes = static_cast<size_t>(N) * (f64 ? 8 : 4);
+    pc.coef = 0;
+    pc.twiddle = align_up(pc.coef_bytes);
+    pc.hpix = pc.twiddle + align_up(pc.twiddle_bytes);
+    const size_t total = pc.hpix + align_up(pc.hpix_bytes);
+    if (hipHostMalloc(&pc.host, total, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        pc.host = nullptr;
+        t->pinned.emplace(key, pc);
+        return nullptr;
+    }
+    char* b = static_cast<char*>(pc.host);
+    if (f64) {
+        std::memcpy(b + pc.coef, t->coef64.data(), pc.coef_bytes);
+        std::memcpy(b + pc.twiddle, twiddles_f64(N).data(), pc.twiddle_bytes);
+        std::memcpy(b + pc.hpix, h.data(), pc.hpix_bytes);
+    } else {
+        std::memcpy(b + pc.coef, t->coef32.data(), pc.coef_bytes);
+        std::memcpy(b + pc.twiddle, twiddles_f32(N).data(), pc.twiddle_bytes);
+        float* hf = reinterpret_cast<float*>(b + pc.hpix);
+        for (int i = 0; i < N; ++i) hf[i] = static_cast<float>(h[i]);
+    }
+    return &t->pinned.emplace(key, pc).first->second;
+}
+
+// Pinned staging for the per-plan block tables, one per host thread. Plan
+// creation does not wait for its uploads; the next creation on the thread
+// waits for the previous one's (an event) before reusing the buffer.
+struct Staging {
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+thread_local Staging g_staging;
+
+void* block_staging(size_t bytes) {
+    thread_local void* buf = nullptr;
+    thread_local size_t cap = 0;
+    if (g_staging.pending) {
+        (void)hipEventSynchronize(g_staging.done);
+        g_staging.pending = false;
+    }
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        if (hipHostMalloc(&buf, bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            buf = nullptr;
+            return nullptr;
+        }
+        cap = bytes;
+    }
+    return buf;
+}
+
+// Pinned slots of 8 ints for the plans' flag readback, from chunks that live
+// until the process ends.
+std::mutex g_slot_mu;
+std::vector<int*> g_free_slots;
+
+int* take_flag_slot() {
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    if (g_free_slots.empty()) {
+        constexpr int kSlots = 1024;
+        void* chunk = nullptr;
+        if (hipHostMalloc(&chunk, kSlots * 16 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        for (int i = 0; i < kSlots; ++i) g_free_slots.push_back(static_cast<int*>(chunk) + 16 * i);
+    }
+    int* s = g_free_slots.back();
+    g_free_slots.pop_back();
+    return s;
+}
+
+void give_flag_slot(int* s) {
+    std::lock_guard<std::mutex> lk(g_slot_mu);
+    g_free_slots.push_back(s);
+}
+
+}  // namespace
+
+lmg_plan::~lmg_plan() {
+    if (ready) {
+        (void)hipEventSynchronize(ready);          // the readback into the pinned slot has landed
+        (void)hipEventDestroy(ready);
+    }
+    if (host_flags) give_flag_slot(host_flags);
+}
+
+namespace {
+
 // Grid rows (or columns) touched by footprints of tiles lo..hi (inclusive),
 // as [r0, r1); the whole range if the footprints wrap around the grid edge.
 void axis_band(int lo, int hi, int T, int W, int N, int ntx, int* r0, int* r1, int* w0, int* wn) {
@@ -277,15 +389,39 @@ void axis_band(int lo, int hi, int T, int W, int N, int ntx, int* r0, int* r1, i
     *wn = std::min(hi + (W > 1 ? 1 : 0), ntx - 1) - lo + 1;
 }
 
-void set_band(lmg_plan* p, int rmin, int rmax, int cmin, int cmax) {
+void set_band(const lmg_plan* p, int rmin, int rmax, int cmin, int cmax) {
     if (p->n_busy == 0) { rmax = -1; cmax = -1; rmin = 0; cmin = 0; }
     axis_band(rmin, rmax, p->g.T, p->g.W, p->g.N, p->g.ntx, &p->band_r0, &p->band_r1, &p->win_r0, &p->win_rn);
     axis_band(cmin, cmax, p->g.T, p->g.W, p->g.N, p->g.ntx, &p->band_c0, &p->band_c1, &p->win_c0, &p->win_cn);
 }
 
+// Parse the plan's counts, waiting for its readback the first time.
+lmg_status ensure_flags(const lmg_plan* p) {
+    std::lock_guard<std::mutex> lk(p->flags_mu);
+    if (p->flags_read) return LMG_OK;
+    LMG_HIP(hipEventSynchronize(p->ready));
+    const int* f = p->host_flags;
+    p->bad_data = f[0] != 0;
+    p->n_items = f[1];
+    p->n_valid = f[2];
+    p->n_busy = f[3];
+    set_band(p, f[4], f[5], f[6], f[7]);
+    p->flags_read = true;
+    if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
+    return LMG_OK;
+}
+
+// A planned call on another stream than the plan's creation waits (on the
+// device) for the plan's kernels.
+lmg_status wait_plan(const lmg_plan* p, hipStream_t s) {
+    LMG_HIP(hipStreamWaitEvent(s, p->ready, 0));
+    return LMG_OK;
+}
+
 lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
                     int* counters, hipStream_t s, bool band_only = false) {
     const lmg_table* t = p->table;
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters, kCounters, s));
     {
         TraceScope ts("permute_in", s);
@@ -293,7 +429,7 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     }
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
-    a.n_items = p->n_items; a.waves = p->waves; a.F = p->F;
+    a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.vis = vs; a.patches = patches; a.counter = counters;
     {
@@ -303,6 +439,8 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     AssembleArgs b{};
     b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx; b.nchan = p->nchan;
     if (band_only) {                  // an internal grid: only the occupied window is ever read
+        const lmg_status st = ensure_flags(p);     // the grid kernels are already queued
+        if (st != LMG_OK) return st;
         b.tr0 = p->win_r0; b.trows = p->win_rn; b.tc0 = p->win_c0; b.tcols = p->win_cn;
     } else {
         b.tr0 = 0; b.trows = p->g.ntx; b.tc0 = 0; b.tcols = p->g.ntx;
@@ -315,10 +453,11 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
 
 lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, int* counters, hipStream_t s) {
     const lmg_table* t = p->table;
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters + 1, 1, s));
     DegridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
-    a.n_items = p->n_items; a.F = p->F;
+    a.n_items = p->flags + 1; a.max_items = p->max_items; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
     {
@@ -339,7 +478,12 @@ FftArgs fft_args(int N, int sign, const void* tw) {
 }
 
 Scratch plan_scratch(const lmg_plan* p, int op) {
-    return scratch_layout(p->g.N, p->g.W, p->g.T, p->M, p->n_items, p->nvis, p->prec, op);
+    // Sized for the most work items this plan can have (its tiles, plus one per cap visibilities), so
+    // that no query waits for its counts.
+    const int64_t bound = std::min<int64_t>(static_cast<int64_t>(p->g.ntiles) * p->nchan, p->nvis) +
+                          (p->nvis + p->cap - 1) / p->cap + 1;
+    return scratch_layout(p->g.N, p->g.W, p->g.T, p->M, static_cast<int>(std::min<int64_t>(bound, p->max_items)),
+                          p->nvis, p->prec, op);
 }
 
 bool scratch_ok(const lmg_plan* p, int op, void* scratch, size_t bytes) {
@@ -423,7 +567,12 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     std::vector<double> h(N);
     if (lmg_correction(table, N, h.data()) != LMG_OK) return LMG_EINVAL;
     std::vector<float> hf(h.begin(), h.end());
-    if (prec == LMG_F64) {
+    if (const lmg_table::Pinned* pc = pinned_constants(table, N, prec, h)) {
+        const char* b = static_cast<const char*>(pc->host);
+        if (upload(p->coef, b + pc->coef, pc->coef_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->twiddle, b + pc->twiddle, pc->twiddle_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->hpix, b + pc->hpix, pc->hpix_bytes, s) != LMG_OK) return LMG_EHIP;
+    } else if (prec == LMG_F64) {
         if (upload(p->coef, table->coef64.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->twiddle, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->hpix, h.data(), sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
@@ -432,9 +581,25 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
         if (upload(p->twiddle, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->hpix, hf.data(), sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
     }
-    if (!blocks.empty() && upload(p->blocks, blocks.data(), blocks.size() * sizeof(int4), s) != LMG_OK)
-        return LMG_EHIP;
-    if (upload(p->chan_blocks, chan_blocks.data(), chan_blocks.size() * sizeof(int), s) != LMG_OK) return LMG_EHIP;
+    {
+        const size_t bb = blocks.size() * sizeof(int4), cb = chan_blocks.size() * sizeof(int);
+        char* st = static_cast<char*>(block_staging(align_up(bb) + cb));
+        const void* bsrc = blocks.data();
+        const void* csrc = chan_blocks.data();
+        if (st) {
+            if (bb) std::memcpy(st, blocks.data(), bb);
+            std::memcpy(st + align_up(bb), chan_blocks.data(), cb);
+            bsrc = st;
+            csrc = st + align_up(bb);
+        }
+        if (bb && upload(p->blocks, bsrc, bb, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->chan_blocks, csrc, cb, s) != LMG_OK) return LMG_EHIP;
+        if (st) {
+            if (!g_staging.done) LMG_HIP(hipEventCreateWithFlags(&g_staging.done, hipEventDisableTiming));
+            LMG_HIP(hipEventRecord(g_staging.done, s));
+            g_staging.pending = true;
+        }
+    }
     LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
     {
         TraceScope ts("plan_count", s);
@@ -462,15 +627,22 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
         TraceScope ts("plan_compose", s);
         LMG_HIP(launch_plan_compose(p->inv0, p->pos2, nvis, p->inv, s));
     }
-    int flags[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    LMG_HIP(hipMemcpyAsync(flags, p->flags, sizeof(flags), hipMemcpyDeviceToHost, s));
-    LMG_HIP(hipStreamSynchronize(s));           // also keeps the uploaded host vectors alive until copied
-    p->bad_data = flags[0] != 0;
-    p->n_items = flags[1];
-    p->n_valid = flags[2];
-    p->n_busy = flags[3];
-    set_band(p.get(), flags[4], flags[5], flags[6], flags[7]);
-    if (p->n_items > p->max_items) return LMG_EHIP;     // cannot happen; guards the scratch bound
+    // Counts come back asynchronously; the host reads them when it first needs them.
+    LMG_HIP(hipEventCreateWithFlags(&p->ready, hipEventDisableTiming));
+    p->host_flags = take_flag_slot();
+    if (p->host_flags) {
+        LMG_HIP(hipMemcpyAsync(p->host_flags, p->flags, 8 * sizeof(int), hipMemcpyDeviceToHost, s));
+        LMG_HIP(hipEventRecord(p->ready, s));
+    } else {                                  // no pinned memory: read back synchronously
+        static thread_local int fallback[8];
+        LMG_HIP(hipMemcpyAsync(fallback, p->flags, sizeof(fallback), hipMemcpyDeviceToHost, s));
+        LMG_HIP(hipEventRecord(p->ready, s));
+        LMG_HIP(hipEventSynchronize(p->ready));
+        p->host_flags = fallback;
+        const lmg_status st = ensure_flags(p.get());
+        p->host_flags = nullptr;
+        if (st != LMG_OK) return st;
+    }
     *out = p.release();
     return LMG_OK;
 }
@@ -519,11 +691,15 @@ const char* lmg_last_error(void) { return g_last_error; }
 
 lmg_status lmg_plan_check(const lmg_plan* p) {
     if (!p) return LMG_EINVAL;
+    const lmg_status st = ensure_flags(p);
+    if (st != LMG_OK) return st;
     return p->bad_data ? LMG_EDATA : LMG_OK;
 }
 
 lmg_status lmg_plan_info(const lmg_plan* p, int* tile, int* n_items, int* n_busy, int64_t* n_valid) {
     if (!p) return LMG_EINVAL;
+    const lmg_status st = ensure_flags(p);
+    if (st != LMG_OK) return st;
     if (tile) *tile = p->g.T;
     if (n_items) *n_items = p->n_items;
     if (n_busy) *n_busy = p->n_busy;
@@ -609,6 +785,11 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
     if (p->nchan != 1) return LMG_ENOTSUP;
     if (!scratch_ok(p, LMG_OP_PREDICT, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
+    {
+        const lmg_status st = ensure_flags(p);     // the occupied band prunes the transforms
+        if (st != LMG_OK) return st;
+    }
     const int N = p->g.N, M = p->M;
     const Scratch L = plan_scratch(p, LMG_OP_PREDICT);
     char* sc = static_cast<char*>(scratch);

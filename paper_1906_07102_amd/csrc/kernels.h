@@ -33,7 +33,9 @@ struct PlanGeom {
 };
 
 struct GridArgs {
-    int N, W, T, ntx, Ms, degree, n_items;
+    int N, W, T, ntx, Ms, degree;
+    const int* n_items;    // device: number of work items (written by the plan)
+    int max_items;         // most work items the plan can have (sizes the launch)
     int waves;             // waves per workgroup, 1..4, each with its own LDS patch
     int F;                 // fraction bits of the packed offsets
     const int4* items;     // (tile, first position, count, pieces)
@@ -54,7 +56,9 @@ struct AssembleArgs {
 };
 
 struct DegridArgs {
-    int N, W, T, ntx, Ms, degree, n_items;
+    int N, W, T, ntx, Ms, degree;
+    const int* n_items;
+    int max_items;
     int F;
     const int4* items;
     const int2* pieces;

@@ -720,12 +720,13 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     const VT* vis = reinterpret_cast<const VT*>(a.vis);     // entry order, weights applied
     const PT2* off = reinterpret_cast<const PT2*>(a.off);   // packed offsets, entry order
+    const int nitems = *a.n_items;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         for (int i = threadIdx.x; i < nw * P2; i += blockDim.x) Acc::zero_cell(&patches[i]);
         __syncthreads();
         const int item = s_item;
-        if (item >= a.n_items) break;                       // uniform across the workgroup
+        if (item >= nitems) break;                       // uniform across the workgroup
         const int4 it = a.items[item];
         constexpr int kB = 4;                               // entries whose loads are issued together
         const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
@@ -859,11 +860,12 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
     const PT2* off = reinterpret_cast<const PT2*>(a.off);
     const int cshift = a.F + 1;
+    const int nitems = *a.n_items;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
         const int item = s_item;
-        if (item >= a.n_items) break;                   // uniform across the workgroup
+        if (item >= nitems) break;                   // uniform across the workgroup
         const int4 it = a.items[item];
         const int chan = it.x / ntiles, lt = it.x % ntiles;
         const int tm = lt / a.ntx, tn = lt % a.ntx;
@@ -1123,7 +1125,7 @@ hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
-    const int nb = std::min(a.n_items, resident_blocks(shm));
+    const int nb = std::min(a.max_items, resident_blocks(shm));
     hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(nb), dim3(64 * a.waves), shm, s, a);
     return hipGetLastError();
 }
@@ -1135,7 +1137,7 @@ hipError_t launch_degrid_w(const DegridArgs& a, hipStream_t s) {
     const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
-    const int nb = std::min(a.n_items, resident_blocks(shm));
+    const int nb = std::min(a.max_items, resident_blocks(shm));
     hipLaunchKernelGGL((dev::k_degrid_items<R, W>), dim3(nb), dim3(256), shm, s, a);
     return hipGetLastError();
 }
@@ -1254,7 +1256,7 @@ hipError_t launch_permute_out(bool f64, const void* vs, const int* inv, int64_t 
 }
 
 hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s) {
-    if (a.n_items == 0) return hipSuccess;
+    if (a.max_items == 0) return hipSuccess;
     switch (prec) {
         case LMG_F32: return dispatch_grid<float, dev::AccF32>(a, s);
         case LMG_F32_KAHAN: return dispatch_grid<float, dev::AccKahan>(a, s);
@@ -1284,7 +1286,7 @@ hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_
 }
 
 hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s) {
-    if (a.n_items == 0) return hipSuccess;
+    if (a.max_items == 0) return hipSuccess;
     return prec == LMG_F64 ? dispatch_degrid<double>(a, s) : dispatch_degrid<float>(a, s);
 }
 

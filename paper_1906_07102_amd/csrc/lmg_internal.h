@@ -36,6 +36,16 @@ struct lmg_table {
     // Correction vectors already computed, by grid size.
     mutable std::mutex cache_mu;
     mutable std::map<int, std::vector<double>> hpix_cache;
+    // Pinned host copies of the constants a plan uploads (coefficients,
+    // twiddles, correction), by (grid size, precision), so that the uploads
+    // are asynchronous. Freed with the table.
+    struct Pinned {
+        void* host = nullptr;
+        size_t coef = 0, twiddle = 0, hpix = 0;      // byte offsets in host
+        size_t coef_bytes = 0, twiddle_bytes = 0, hpix_bytes = 0;
+    };
+    mutable std::map<std::pair<int, int>, Pinned> pinned;
+    ~lmg_table();
 };
 
 namespace lmg {

@@ -12,6 +12,8 @@
 #include <new>
 #include <vector>
 
+#include <hip/hip_runtime.h>
+
 #include "lmg_internal.h"
 
 namespace lmg {
@@ -539,3 +541,8 @@ const char* lmg_status_string(lmg_status s) {
 }
 
 }  // extern "C"
+
+lmg_table::~lmg_table() {
+    for (auto& kv : pinned)
+        if (kv.second.host) (void)hipHostFree(kv.second.host);
+}

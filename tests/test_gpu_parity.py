@@ -265,3 +265,23 @@ def test_full_size_grid_degrid_sampled(which):
     out = plan.degrid(to_dev(G, torch.complex64))
     k = rng.integers(0, len(c.uv), 2000)
     assert rel_rms(out[k].cpu().numpy(), im.degrid(c.uv[k], G.astype(np.complex128), otab)) < 1e-5
+
+
+def test_plan_used_from_another_stream():
+    """Plan creation only enqueues work; a call on another stream waits for the plan on the device."""
+    print("plan on one stream, calls on another", flush=True)
+    uv, vis, w, _ = small()
+    otab, gtab, _ = tables(7, 3)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    duv = to_dev(uv, torch.float64)
+    dvis = to_dev(vis, torch.complex128)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        plan = lmg.Plan(gtab, 128, duv, lmg.F64)
+    with torch.cuda.stream(s2):
+        g = plan.grid(dvis)
+        v = plan.degrid(g)
+    torch.cuda.synchronize()
+    assert plan.info()["items"] > 0
+    assert rel_rms(g.cpu().numpy(), im.grid(uv, vis, None, 128, otab)) < 1e-12
+    assert rel_rms(v.cpu().numpy(), im.degrid(uv, g.cpu().numpy(), otab)) < 1e-12
