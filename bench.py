@@ -346,17 +346,30 @@ def main():
         plan.predict_visibilities(img, out=vout)
         return plan
 
+    # After the warm-up, two steps record every kernel (HIP events on the launch stream) for the
+    # per-kernel table; the kernel with the most time per launch is the one the roofline is quoted
+    # for. In the timed steps only that kernel is recorded, so that its duration is measured over the
+    # timed region with little tracing overhead.
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     lmg.trace_report()                       # discard anything recorded so far
     lmg.trace_enable(True)
+    lmg.trace_only(None)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    trace = lmg.trace_report()
+    dom = max(trace.items(), key=lambda kv: kv[1][1] / kv[1][0])[0]
+    lmg.trace_only(dom)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         plan = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    trace = lmg.trace_report()
+    dom_trace = lmg.trace_report()[dom]
+    lmg.trace_only(None)
     lmg.trace_enable(False)
     ms = (t1 - t0) * 1e3 / args.steps
     print(f"# step {ms:.3f} ms; plan {plan.info()}", file=sys.stderr, flush=True)
@@ -381,8 +394,8 @@ def main():
         kernels[name] = {"launches": n, "avg_ms": round(avg, 5),
                          "algorithmic_GBps": round(ab / (avg * 1e-3) / 1e9, 1) if ab else None,
                          "traffic": load_traffic(name, nvis)}
-    dom = max(trace.items(), key=lambda kv: kv[1][1])[0]
-    dom_avg_s = trace[dom][1] / trace[dom][0] * 1e-3
+    dom_avg_s = dom_trace[1] / dom_trace[0] * 1e-3
+    kernels[dom]["avg_ms_timed_region"] = round(dom_avg_s * 1e3, 5)
     ab = algorithmic_bytes(dom, nvis, N, M, cs)
     achieved = ab / dom_avg_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

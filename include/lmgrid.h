@@ -253,6 +253,9 @@ lmg_status lmg_fft2_centred(int N, lmg_precision prec, int sign, void* data, voi
  * with respect to concurrent launches from several host threads. */
 lmg_status lmg_trace_enable(int on);
 lmg_status lmg_trace_report(char* buf, size_t len);
+/* Record only the kernel of this trace name ("grid_items", "plan_scatter",
+ * ...); NULL or "" records every kernel again. The name is copied. */
+lmg_status lmg_trace_only(const char* name);
 
 const char* lmg_status_string(lmg_status s);
 

@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "F32", "F32_KAHAN", "F64", "LmgError", "LibraryMissing", "Table", "Plan", "BatchPlan", "autotune_batch",
     "library_path", "load", "grid", "degrid", "make_dirty_image", "predict_visibilities", "grid_batched",
-    "degrid_batched", "fft2_centred", "trace_enable", "trace_report", "Degrid", "Grid", "PredictVisibilities",
+    "degrid_batched", "fft2_centred", "trace_enable", "trace_only", "trace_report", "Degrid", "Grid", "PredictVisibilities",
     "MakeDirtyImage",
 ]
 
@@ -103,6 +103,7 @@ def load():
         "lmg_degrid_batched": (I, [P, I, I, I, ctypes.POINTER(I64), P, P, P, P, Z, P]),
         "lmg_trace_enable": (I, [I]),
         "lmg_trace_report": (I, [ctypes.c_char_p, Z]),
+        "lmg_trace_only": (I, [ctypes.c_char_p]),
         "lmg_status_string": (ctypes.c_char_p, [I]),
         "lmg_last_error": (ctypes.c_char_p, []),
     }
@@ -670,6 +671,11 @@ def predict_visibilities(table: Table, N: int, uv, image, stream=None):
 def trace_enable(on: bool = True):
     """Bracket every library kernel launch with HIP events (per-kernel timing)."""
     _check(load().lmg_trace_enable(1 if on else 0), "lmg_trace_enable")
+
+
+def trace_only(name: Optional[str] = None):
+    """Record only the named kernel (None: all kernels again)."""
+    _check(load().lmg_trace_only(None if name is None else name.encode()), "lmg_trace_only")
 
 
 def trace_report() -> dict:

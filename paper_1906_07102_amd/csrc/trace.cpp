@@ -19,7 +19,18 @@ struct Rec {
 };
 std::mutex g_mu;
 std::vector<Rec> g_recs;
+std::vector<hipEvent_t> g_pool;     // events for reuse (creating events costs more than recording them)
+std::string g_only;                 // if set, only this kernel name is recorded
 int g_on = -1;      // -1: not yet read from the environment
+
+bool take(hipEvent_t* e) {
+    if (!g_pool.empty()) {
+        *e = g_pool.back();
+        g_pool.pop_back();
+        return true;
+    }
+    return hipEventCreate(e) == hipSuccess;
+}
 
 bool enabled() {
     if (g_on < 0) {
@@ -33,9 +44,10 @@ bool enabled() {
 TraceScope::TraceScope(const char* name, hipStream_t s) : name_(name), s_(s) {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!enabled()) return;
-    if (hipEventCreate(&a_) != hipSuccess) return;
-    if (hipEventCreate(&b_) != hipSuccess) { (void)hipEventDestroy(a_); return; }
-    if (hipEventRecord(a_, s_) != hipSuccess) { (void)hipEventDestroy(a_); (void)hipEventDestroy(b_); return; }
+    if (!g_only.empty() && g_only != name) return;
+    if (!take(&a_)) return;
+    if (!take(&b_)) { g_pool.push_back(a_); return; }
+    if (hipEventRecord(a_, s_) != hipSuccess) { g_pool.push_back(a_); g_pool.push_back(b_); return; }
     active_ = true;
 }
 
@@ -56,6 +68,12 @@ lmg_status lmg_trace_enable(int on) {
     return LMG_OK;
 }
 
+lmg_status lmg_trace_only(const char* name) {
+    std::lock_guard<std::mutex> lk(lmg::g_mu);
+    lmg::g_only = name ? name : "";
+    return LMG_OK;
+}
+
 lmg_status lmg_trace_report(char* buf, size_t len) {
     if (!buf || len == 0) return LMG_EINVAL;
     std::lock_guard<std::mutex> lk(lmg::g_mu);
@@ -69,8 +87,8 @@ lmg_status lmg_trace_report(char* buf, size_t len) {
         auto& e = acc[r.name];
         e.first += 1;
         e.second += ms;
-        (void)hipEventDestroy(r.a);
-        (void)hipEventDestroy(r.b);
+        lmg::g_pool.push_back(r.a);
+        lmg::g_pool.push_back(r.b);
     }
     lmg::g_recs.clear();
     std::string out;
