@@ -600,7 +600,7 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
             g_staging.pending = true;
         }
     }
-    LMG_HIP(hipMemsetAsync(p->flags, 0, 16 * sizeof(int), s));
+    LMG_HIP(launch_zero_ints(p->flags, 16, s));          // a kernel, not a memset node, if captured
     {
         TraceScope ts("plan_count", s);
         LMG_HIP(launch_plan_count(uv, p->blocks, p->nblocks, p->g, p->blockhist, p->flags, s));

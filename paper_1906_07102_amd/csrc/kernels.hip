@@ -431,19 +431,32 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
             if (t) atomicAdd(&lcnt[t], 1);
         }
         __syncthreads();
-        if (threadIdx.x == 0) {                          // piece slots: full by level, then tails by length
-            int a = 0;
-            for (int q = 0; q < kMaxCap / kPiece + 1; ++q) {
-                const int x = qcnt[q];
-                qcnt[q] = a;
-                a += x;
+        if (threadIdx.x < 64) {                          // piece slots: full by level, then tails by length
+            // Wave 0: each lane owns a run of levels (then one tail length, longest first) and the
+            // wave scans the run totals.
+            constexpr int kLevels = kMaxCap / kPiece + 1;
+            constexpr int kPer = (kLevels + 63) / 64;
+            const int ln = threadIdx.x;
+            int run = 0;
+            for (int i = 0; i < kPer; ++i) {
+                const int q = ln * kPer + i;
+                if (q < kLevels) run += qcnt[q];
             }
-            for (int l = kPiece - 1; l >= 1; --l) {
-                const int x = lcnt[l];
-                lcnt[l] = a;
-                a += x;
+            const int tail = (ln < kPiece - 1) ? lcnt[kPiece - 1 - ln] : 0;   // lengths 31 .. 1
+            const int inc_q = wave_incl_sum(run);
+            const int total_q = __shfl(inc_q, 63, 64);
+            int a = inc_q - run;
+            for (int i = 0; i < kPer; ++i) {
+                const int q = ln * kPer + i;
+                if (q < kLevels) {
+                    const int x = qcnt[q];
+                    qcnt[q] = a;
+                    a += x;
+                }
             }
-            items[item].w = a;
+            const int inc_t = wave_incl_sum(tail);
+            if (ln < kPiece - 1) lcnt[kPiece - 1 - ln] = total_q + inc_t - tail;
+            if (ln == 63) items[item].w = total_q + inc_t;
         }
         __syncthreads();
         for (int c = c0; c < c1; ++c) {
