@@ -261,6 +261,43 @@ __global__ __launch_bounds__(64 * kScanGroups) void k_plan_colscan(PlanGeom g, i
     if (live && grp == kScanGroups - 1) tile_count[slot] = run;
 }
 
+struct ScanAcc {
+    int s, si, busy, rmin, rmax, cmin, cmax;
+};
+
+__device__ __forceinline__ void scan_sum(int t, int c, int tot, int cap, int& s, int& si) {
+    s += c;
+    if (t < tot) si += (c + cap - 1) / cap;
+}
+
+// Offsets of slot t (count c) and its work items; slot tot holds the dropped visibilities.
+__device__ __forceinline__ void scan_place(const PlanGeom& g, int t, int c, int tot, int cap, int* tile_start,
+                                           int* item_start, int4* items, int* flags, ScanAcc& a) {
+    tile_start[t] = a.s;
+    if (t == tot) {
+        flags[2] = a.s;
+        a.s += c;
+        return;
+    }
+    const int ni = (c + cap - 1) / cap;
+    item_start[t] = a.si;
+    if (c > 0) {
+        const int lt = t % g.ntiles;
+        a.rmin = min(a.rmin, lt / g.ntx);
+        a.rmax = max(a.rmax, lt / g.ntx);
+        a.cmin = min(a.cmin, lt % g.ntx);
+        a.cmax = max(a.cmax, lt % g.ntx);
+    }
+    for (int q = 0; q < ni; ++q) {
+        const int lo = static_cast<int>((static_cast<int64_t>(c) * q) / ni);
+        const int hi = static_cast<int>((static_cast<int64_t>(c) * (q + 1)) / ni);
+        items[a.si + q] = make_int4(t, a.s + lo, hi - lo, 0);
+    }
+    a.busy += (c > 0);
+    a.s += c;
+    a.si += ni;
+}
+
 // Pass 2 (one workgroup): slot offsets, work items of at most `cap`
 // visibilities, counts and the occupied band (flags[1] items, [2] valid
 // visibilities, [3] busy tiles, [4..7] min / max occupied tile row and
@@ -273,42 +310,36 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
     const int ns = tot + 1;
     const int per = (ns + blockDim.x - 1) / blockDim.x;
     const int lo = threadIdx.x * per, hi = min(ns, lo + per);
+    // Up to kReg counts per thread are held in registers (loaded together, read twice); larger
+    // problems (many channels) read them from memory.
+    constexpr int kReg = 24;
+    const bool in_regs = per <= kReg;
+    int creg[kReg];
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kReg; ++i) creg[i] = (lo + i < hi) ? tile_count[lo + i] : 0;
+    }
     int s = 0, si = 0;
-    for (int t = lo; t < hi; ++t) {
-        s += tile_count[t];
-        if (t < tot) si += (tile_count[t] + cap - 1) / cap;
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kReg; ++i)
+            if (lo + i < hi) scan_sum(lo + i, creg[i], tot, cap, s, si);
+    } else {
+        for (int t = lo; t < hi; ++t) scan_sum(t, tile_count[t], tot, cap, s, si);
     }
     int nvis = 0, nitems = 0;
     s = block_excl_sum(s, sh, &nvis);
     si = block_excl_sum(si, sh, &nitems);
-    int busy = 0;
-    int rmin = 1 << 30, rmax = -1, cmin = 1 << 30, cmax = -1;
-    for (int t = lo; t < hi; ++t) {
-        const int c = tile_count[t];
-        tile_start[t] = s;
-        if (t == tot) {                            // dropped visibilities: no items
-            flags[2] = s;
-            s += c;
-            continue;
-        }
-        const int ni = (c + cap - 1) / cap;
-        item_start[t] = si;
-        if (c > 0) {
-            const int lt = t % g.ntiles;
-            rmin = min(rmin, lt / g.ntx);
-            rmax = max(rmax, lt / g.ntx);
-            cmin = min(cmin, lt % g.ntx);
-            cmax = max(cmax, lt % g.ntx);
-        }
-        for (int q = 0; q < ni; ++q) {
-            const int a = static_cast<int>((static_cast<int64_t>(c) * q) / ni);
-            const int b = static_cast<int>((static_cast<int64_t>(c) * (q + 1)) / ni);
-            items[si + q] = make_int4(t, s + a, b - a, 0);
-        }
-        busy += (c > 0);
-        s += c;
-        si += ni;
+    ScanAcc acc{s, si, 0, 1 << 30, -1, 1 << 30, -1};
+    if (in_regs) {
+#pragma unroll
+        for (int i = 0; i < kReg; ++i)
+            if (lo + i < hi) scan_place(g, lo + i, creg[i], tot, cap, tile_start, item_start, items, flags, acc);
+    } else {
+        for (int t = lo; t < hi; ++t)
+            scan_place(g, t, tile_count[t], tot, cap, tile_start, item_start, items, flags, acc);
     }
+    int busy = acc.busy, rmin = acc.rmin, rmax = acc.rmax, cmin = acc.cmin, cmax = acc.cmax;
     busy = block_reduce(busy, 2, sh);
     rmin = block_reduce(rmin, 0, sh);
     rmax = block_reduce(rmax, 1, sh);
