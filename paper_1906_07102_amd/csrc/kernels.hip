@@ -265,33 +265,52 @@ struct ScanAcc {
     int s, si, busy, rmin, rmax, cmin, cmax;
 };
 
+// Work items of a slot with c visibilities: ceil(c / cap); the division is
+// only taken for the rare slots above cap (this single-workgroup pass is
+// bound by its instruction count).
+__device__ __forceinline__ int slot_items(int c, int cap) {
+    return c <= cap ? (c > 0 ? 1 : 0) : (c + cap - 1) / cap;
+}
+
 __device__ __forceinline__ void scan_sum(int t, int c, int tot, int cap, int& s, int& si) {
     s += c;
-    if (t < tot) si += (c + cap - 1) / cap;
+    if (t < tot) si += slot_items(c, cap);
 }
 
 // Offsets of slot t (count c) and its work items; slot tot holds the dropped visibilities.
 __device__ __forceinline__ void scan_place(const PlanGeom& g, int t, int c, int tot, int cap, int* tile_start,
-                                           int* item_start, int4* items, int* flags, ScanAcc& a) {
+                                           int* item_start, int4* items, int* flags, ScanAcc& a, bool write_items) {
     tile_start[t] = a.s;
     if (t == tot) {
         flags[2] = a.s;
         a.s += c;
         return;
     }
-    const int ni = (c + cap - 1) / cap;
+    const int ni = slot_items(c, cap);
     item_start[t] = a.si;
     if (c > 0) {
-        const int lt = t % g.ntiles;
-        a.rmin = min(a.rmin, lt / g.ntx);
-        a.rmax = max(a.rmax, lt / g.ntx);
-        a.cmin = min(a.cmin, lt % g.ntx);
-        a.cmax = max(a.cmax, lt % g.ntx);
+        // tiles per row and tiles per channel are powers of two
+        const int lbx = __builtin_ctz(static_cast<unsigned>(g.ntx));
+        const int lt = t & (g.ntiles - 1);
+        const int tr = lt >> lbx, tc = lt & (g.ntx - 1);
+        a.rmin = min(a.rmin, tr);
+        a.rmax = max(a.rmax, tr);
+        a.cmin = min(a.cmin, tc);
+        a.cmax = max(a.cmax, tc);
     }
-    for (int q = 0; q < ni; ++q) {
-        const int lo = static_cast<int>((static_cast<int64_t>(c) * q) / ni);
-        const int hi = static_cast<int>((static_cast<int64_t>(c) * (q + 1)) / ni);
-        items[a.si + q] = make_int4(t, a.s + lo, hi - lo, 0);
+    if (!write_items) {
+    } else if (ni == 1) {
+        items[a.si] = make_int4(t, a.s, c, 0);
+    } else if (ni > 1) {
+        // even split: the first c % ni items take one visibility more (32-bit arithmetic: the dense
+        // central tiles are consecutive slots of one thread, and a wide division per item serialises it)
+        const int base = c / ni, extra = c - base * ni;
+        int lo = 0;
+        for (int q = 0; q < ni; ++q) {
+            const int n = base + (q < extra ? 1 : 0);
+            items[a.si + q] = make_int4(t, a.s + lo, n, 0);
+            lo += n;
+        }
     }
     a.busy += (c > 0);
     a.s += c;
@@ -302,42 +321,82 @@ __device__ __forceinline__ void scan_place(const PlanGeom& g, int t, int c, int 
 // visibilities, counts and the occupied band (flags[1] items, [2] valid
 // visibilities, [3] busy tiles, [4..7] min / max occupied tile row and
 // column). tile_start has nslots + 1 entries (the last is nvis).
+// Each thread scans a contiguous run of slots. With `staged` (slots fit
+// twice in LDS) the counts come in, and the slot and item offsets go out,
+// through LDS, so that global accesses are coalesced and the per-slot loop
+// waits only on LDS, not on the global stores of the work items.
+template <bool kStaged>
+__device__ __forceinline__ void scan_slots(const PlanGeom& g, const int* cnt, int* start_out, int* items_out, int lo,
+                                           int hi, int tot, int cap, int4* items, int* flags, int* sh, int* nvis,
+                                           int* nitems, ScanAcc& acc) {
+    int s = 0, si = 0;
+#pragma unroll 1
+    for (int t = lo; t < hi; ++t) scan_sum(t, cnt[t], tot, cap, s, si);
+    // (the barriers inside also order every read of staged counts by other threads before the
+    // overwrites below; a thread reads its own slot before overwriting it)
+    s = block_excl_sum(s, sh, nvis);
+    si = block_excl_sum(si, sh, nitems);
+    acc = ScanAcc{s, si, 0, 1 << 30, -1, 1 << 30, -1};
+#pragma unroll 1
+    for (int t = lo; t < hi; ++t) {
+        const int c = cnt[t];
+        scan_place(g, t, c, tot, cap, start_out, items_out, items, flags, acc, !kStaged);
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __restrict__ tile_count,
                                                     int* __restrict__ tile_start, int* __restrict__ item_start,
-                                                    int4* __restrict__ items, int* __restrict__ flags, int cap) {
-    __shared__ int sh[17];
+                                                    int4* __restrict__ items, int* __restrict__ flags, int cap,
+                                                    int staged) {
+    extern __shared__ int lds[];
+    int* sh = lds;                               // 17 ints for the block reductions
     const int tot = g.ntiles * g.nchan;          // tile slots, channel-major; slot tot = dropped
     const int ns = tot + 1;
     const int per = (ns + blockDim.x - 1) / blockDim.x;
     const int lo = threadIdx.x * per, hi = min(ns, lo + per);
-    // Up to kReg counts per thread are held in registers (loaded together, read twice); larger
-    // problems (many channels) read them from memory.
-    constexpr int kReg = 24;
-    const bool in_regs = per <= kReg;
-    int creg[kReg];
-    if (in_regs) {
-#pragma unroll
-        for (int i = 0; i < kReg; ++i) creg[i] = (lo + i < hi) ? tile_count[lo + i] : 0;
-    }
-    int s = 0, si = 0;
-    if (in_regs) {
-#pragma unroll
-        for (int i = 0; i < kReg; ++i)
-            if (lo + i < hi) scan_sum(lo + i, creg[i], tot, cap, s, si);
-    } else {
-        for (int t = lo; t < hi; ++t) scan_sum(t, tile_count[t], tot, cap, s, si);
-    }
     int nvis = 0, nitems = 0;
-    s = block_excl_sum(s, sh, &nvis);
-    si = block_excl_sum(si, sh, &nitems);
-    ScanAcc acc{s, si, 0, 1 << 30, -1, 1 << 30, -1};
-    if (in_regs) {
+    ScanAcc acc;
+    if (staged) {
+        int* s_start = lds + 32;                 // counts, then slot offsets
+        int* s_items = s_start + ns;             // item offsets
+        constexpr int kL = 8;                    // loads in flight per thread
+        for (int t0 = 0; t0 < ns; t0 += kL * blockDim.x) {
+            int v[kL];
 #pragma unroll
-        for (int i = 0; i < kReg; ++i)
-            if (lo + i < hi) scan_place(g, lo + i, creg[i], tot, cap, tile_start, item_start, items, flags, acc);
+            for (int u = 0; u < kL; ++u) {
+                const int t = t0 + u * blockDim.x + threadIdx.x;
+                v[u] = t < ns ? tile_count[t] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kL; ++u) {
+                const int t = t0 + u * blockDim.x + threadIdx.x;
+                if (t < ns) s_start[t] = v[u];
+            }
+        }
+        __syncthreads();
+        scan_slots<true>(g, s_start, s_start, s_items, lo, hi, tot, cap, items, flags, sh, &nvis, &nitems, acc);
+        if (threadIdx.x == 0) s_items[tot] = nitems;
+        __syncthreads();
+        for (int t = threadIdx.x; t < ns; t += blockDim.x) tile_start[t] = s_start[t];
+        for (int t = threadIdx.x; t < tot; t += blockDim.x) item_start[t] = s_items[t];
+        // Work items in parallel (a tile above cap has several, and the dense tiles are neighbours in
+        // one thread's run): item i belongs to the last slot whose first item is <= i.
+        for (int i = threadIdx.x; i < nitems; i += blockDim.x) {
+            int a = 0, b = tot;                  // s_items[a] <= i < s_items[b]
+            while (b - a > 1) {
+                const int m = (a + b) >> 1;
+                if (s_items[m] <= i) a = m; else b = m;
+            }
+            const int c = s_start[a + 1] - s_start[a];
+            const int ni = slot_items(c, cap);
+            const int q = i - s_items[a];
+            const int base = c / ni, extra = c - base * ni;     // the first extra items take one more
+            const int lo = q * base + min(q, extra);
+            items[i] = make_int4(a, s_start[a] + lo, base + (q < extra ? 1 : 0), 0);
+        }
     } else {
-        for (int t = lo; t < hi; ++t)
-            scan_place(g, t, tile_count[t], tot, cap, tile_start, item_start, items, flags, acc);
+        scan_slots<false>(g, tile_count, tile_start, item_start, lo, hi, tot, cap, items, flags, sh, &nvis, &nitems,
+                          acc);
     }
     int busy = acc.busy, rmin = acc.rmin, rmax = acc.rmax, cmin = acc.cmin, cmax = acc.cmax;
     busy = block_reduce(busy, 2, sh);
@@ -513,11 +572,26 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
 
 // Pass 5: caller index -> entry index, composed once so that the per-call
 // permutations need a single lookup: inv[k] = pos2[inv0[k]] (-1: dropped).
+// Each thread handles kComposeE indices a block apart, so that that many
+// independent gathers are in flight per thread.
+constexpr int kComposeE = 8;
 __global__ __launch_bounds__(256) void k_plan_compose(const int* __restrict__ inv0, const int* __restrict__ pos2,
                                                       int64_t nvis, int* __restrict__ inv) {
-    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
-    if (k >= nvis) return;
-    inv[k] = pos2[inv0[k]];
+    const int64_t base = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * (blockDim.x * kComposeE) + threadIdx.x;
+    int d[kComposeE];
+#pragma unroll
+    for (int e = 0; e < kComposeE; ++e) {
+        const int64_t k = base + e * blockDim.x;
+        d[e] = k < nvis ? inv0[k] : 0;               // 0: a valid position (nvis > 0), result unused
+    }
+    int r[kComposeE];
+#pragma unroll
+    for (int e = 0; e < kComposeE; ++e) r[e] = pos2[d[e]];
+#pragma unroll
+    for (int e = 0; e < kComposeE; ++e) {
+        const int64_t k = base + e * blockDim.x;
+        if (k < nvis) inv[k] = r[e];
+    }
 }
 
 // Caller order -> entry order: vs[inv[k]] = w_k V_k. Reads are sequential;
@@ -539,18 +613,34 @@ __global__ __launch_bounds__(256) void k_permute_in(const typename C2<R>::T* __r
     vs[d] = v;
 }
 
-// Entry order -> caller order: out[k] = vs[inv[k]], zero for dropped visibilities.
+// Entry order -> caller order: out[k] = vs[inv[k]], zero for dropped
+// visibilities. kPermOutE indices a block apart per thread, so that several
+// gathers are in flight per thread. (The scattering direction, k_permute_in,
+// keeps one index per thread: there more in flight spreads the writes to a
+// line over a longer time and L2 merges fewer of them.)
+constexpr int kPermOutE = 4;
 template <typename R>
 __global__ __launch_bounds__(256) void k_permute_out(const typename C2<R>::T* __restrict__ vs, const int* __restrict__ inv,
                                                      int64_t nvis, typename C2<R>::T* __restrict__ out) {
-    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
-    if (k >= nvis) return;
-    const int d = inv[k];
-    typename C2<R>::T v;
-    v.x = 0;
-    v.y = 0;
-    if (d >= 0) v = vs[d];
-    out[k] = v;
+    const int64_t base = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * (blockDim.x * kPermOutE) + threadIdx.x;
+    int d[kPermOutE];
+#pragma unroll
+    for (int e = 0; e < kPermOutE; ++e) {
+        const int64_t k = base + e * blockDim.x;
+        d[e] = k < nvis ? inv[k] : -1;
+    }
+    typename C2<R>::T v[kPermOutE];
+#pragma unroll
+    for (int e = 0; e < kPermOutE; ++e) {
+        v[e].x = 0;
+        v[e].y = 0;
+        if (d[e] >= 0) v[e] = vs[d[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < kPermOutE; ++e) {
+        const int64_t k = base + e * blockDim.x;
+        if (k < nvis) out[k] = v[e];
+    }
 }
 
 // K consecutive elements from p into out. 8-byte elements travel in 16-byte
@@ -1226,8 +1316,14 @@ hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* cha
 
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
                             int* flags, int cap, hipStream_t s) {
-    hipLaunchKernelGGL(dev::k_plan_scan, dim3(1), dim3(1024), 0, s, g, tile_count, tile_start, item_start, items,
-                       flags, cap);
+    // Staged through LDS when the counts and two offset arrays fit (and the
+    // per-thread run fits the kernel's registers: ns <= 1024 * 24).
+    const size_t ns = static_cast<size_t>(g.ntiles) * g.nchan + 1;
+    const size_t staged_bytes = (32 + 2 * ns) * sizeof(int);
+    const int staged = (staged_bytes <= kMaxDynLds && ns <= 1024 * 24) ? 1 : 0;
+    const size_t shm = staged ? staged_bytes : 32 * sizeof(int);
+    hipLaunchKernelGGL(dev::k_plan_scan, dim3(1), dim3(1024), shm, s, g, tile_count, tile_start, item_start, items,
+                       flags, cap, staged);
     return hipGetLastError();
 }
 
@@ -1269,7 +1365,8 @@ hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_it
 
 hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s) {
     if (nvis == 0) return hipSuccess;
-    hipLaunchKernelGGL(dev::k_plan_compose, dim3(static_cast<unsigned>((nvis + 255) / 256)), dim3(256), 0, s, inv0,
+    const int64_t per = 256 * dev::kComposeE;
+    hipLaunchKernelGGL(dev::k_plan_compose, dim3(static_cast<unsigned>((nvis + per - 1) / per)), dim3(256), 0, s, inv0,
                        pos2, nvis, inv);
     return hipGetLastError();
 }
@@ -1289,7 +1386,8 @@ hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const in
 
 hipError_t launch_permute_out(bool f64, const void* vs, const int* inv, int64_t nvis, void* out, hipStream_t s) {
     if (nvis == 0) return hipSuccess;
-    const unsigned nb = static_cast<unsigned>((nvis + 255) / 256);
+    const int64_t per = 256 * dev::kPermOutE;
+    const unsigned nb = static_cast<unsigned>((nvis + per - 1) / per);
     if (f64)
         hipLaunchKernelGGL(dev::k_permute_out<double>, dim3(nb), dim3(256), 0, s,
                            reinterpret_cast<const double2*>(vs), inv, nvis, reinterpret_cast<double2*>(out));
@@ -1383,6 +1481,7 @@ hipError_t set_kernel_attributes() {
         hipFuncAttributeMaxDynamicSharedMemorySize, bytes); if (r != hipSuccess) e = r; } while (0)
     // Per-tile histograms of up to 128 x 128 ints; the item sort keeps two per-cell arrays of up to 128 x 128.
     LMG_ATTR(72 * 1024, &dev::k_plan_count);
+    LMG_ATTR(kMaxDynLds, &dev::k_plan_scan);
     LMG_ATTR(72 * 1024, &dev::k_plan_scatter<float>);
     LMG_ATTR(72 * 1024, &dev::k_plan_scatter<double>);
     LMG_ATTR(128 * 1024, &dev::k_plan_sort_items<float>);
