@@ -160,6 +160,45 @@ def summarize_traffic(fetch_csv: str, write_csv: str, command: str, nvis: int):
     return "\n".join(lines) + "\n", data
 
 
+READ_SIZE_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+
+
+def summarize_read_sizes(csv_path: str, command: str, nvis: int) -> str:
+    """Read bytes per launch from the L2 -> memory read requests counted by size (one --pmc pass with the four
+    READ_SIZE_COUNTERS). FETCH_SIZE takes every request it cannot size as 64 bytes, so a kernel issuing
+    128-byte requests reads as half its bytes (the copy's factor 2) and one issuing narrower requests is
+    over-counted by that factor; sizing each request removes the calibration."""
+    per = {c: _counter_per_dispatch(csv_path, c) for c in READ_SIZE_COUNTERS}
+    n, n32, n64, n128 = (per[c] for c in READ_SIZE_COUNTERS)
+
+    def sized(name):
+        a, b, c, d = (np.array(x[name], dtype=float) for x in (n, n32, n64, n128))
+        rest = np.maximum(a - b - c - d, 0.0)
+        return 32 * b + 64 * c + 128 * d + 64 * rest, a, b, c, d
+
+    lines = ["# HBM read bytes per launch from read requests counted by size (L2 -> memory)",
+             f"# command: {command}",
+             "# bytes = 32 x RDREQ_32B + 64 x RDREQ_64B + 128 x RDREQ_128B (+ 64 x any unsized request)", ""]
+    cal = [k for k in n if CALIBRATION_SYMBOL in k]
+    if cal:
+        by, *_ = sized(cal[0])
+        big = by[by > CALIBRATION_BYTES / 2]
+        if len(big):
+            lines.append(f"calibration copy (1 GiB read): {float(np.median(big)) / CALIBRATION_BYTES:.4f} GiB read")
+    lines += [f"# nvis {nvis}", "",
+              f"{'trace name':24s} {'kernel':44s} {'read_MB':>9s} {'B/vis':>7s} {'32B':>6s} {'64B':>6s} {'128B':>6s}"]
+    for trace, sym in TRACE_TO_SYMBOL.items():
+        names = [k for k in n if k.startswith(sym + "<") or k == sym]
+        if not names:
+            continue
+        by, a, b, c, d = sized(names[0])
+        i = int(np.argsort(by)[len(by) // 2])
+        tot = max(a[i], 1.0)
+        lines.append(f"{trace:24s} {names[0][:44]:44s} {by[i] / 1e6:9.2f} {by[i] / nvis:7.2f} "
+                     f"{b[i] / tot:6.2f} {c[i] / tot:6.2f} {d[i] / tot:6.2f}")
+    return "\n".join(lines) + "\n"
+
+
 def cpu_baseline(case, nvis_sample: int):
     """The FP64 oracle on a bounded sample of the same workload, scaled to visibilities/s of a whole step."""
     from oracle import imaging as im
@@ -297,11 +336,16 @@ def main():
                     help="print a text summary of a rocprofv3 --stats run and exit (no GPU use)")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from FETCH_SIZE and WRITE_SIZE passes, print a summary, exit")
+    ap.add_argument("--summarize-read-sizes", metavar="COUNTER_CSV",
+                    help="print read bytes per launch from a pass with the sized read-request counters, exit")
     ap.add_argument("--profile-command", default="", help="command line recorded in a summary")
     ap.add_argument("--nvis", type=int, default=16777152, help="visibilities of the profiled run (traffic summary)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.profile_command), end="")
+        return
+    if args.summarize_read_sizes:
+        print(summarize_read_sizes(args.summarize_read_sizes, args.profile_command, args.nvis), end="")
         return
     if args.summarize_traffic:
         text, data = summarize_traffic(*args.summarize_traffic, args.profile_command, args.nvis)

@@ -463,14 +463,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
     }
 }
 
-// Pass 4 (workgroups loop over items): order the item's visibilities by
-// footprint cell (counting sort in LDS) into packed offsets `off` (entry
-// order), with pos2 (tile-order position -> entry), and cut each cell's run
-// into pieces of at most kPiece. Full pieces come first, interleaved over cells (all first
-// pieces of every cell, then all second pieces, ...) so that lanes of one
-// wave hold different cells; then the shorter tails, longest first, so that
-// a wave's lanes run loops of similar length. items[i].w receives the number
-// of pieces; the pieces occupy pieces[item start ...]. Dropped visibilities
+// Pass 4 (workgroups loop over items): order the item's visibilities into
+// pieces (at most kPiece visibilities of one footprint cell) and lay the
+// entries out in piece order, so that a round of the gridding kernel, which
+// takes consecutive pieces, reads one contiguous range. Piece order: the full
+// pieces, cell by cell (cell c's f = n / kPiece pieces at F(c) .. F(c)+f-1,
+// F an exclusive prefix of f), then the tails, longest first (a wave's lanes
+// run loops of similar length). Outputs: packed offsets `off` by entry,
+// pos2 (tile-order position -> entry), pieces[] (first entry, length |
+// cell << 16) and items[i].w = number of pieces. Dropped visibilities
 // (tile-order positions n_valid .. nvis) get pos2 = -1.
 template <typename R>
 __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __restrict__ items,
@@ -480,31 +481,37 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
                                                          int* __restrict__ pos2, int2* __restrict__ pieces) {
     extern __shared__ int sm[];
     __shared__ int part[256];
-    __shared__ int qcnt[kMaxCap / kPiece + 1];
-    __shared__ int lcnt[kPiece];
+    __shared__ int lcnt[kPiece];        // tails per length, then slot cursors
+    __shared__ int lfirst[kPiece];      // first tail slot of each length
+    __shared__ int lbase[kPiece];       // first entry of each length's tails
+    __shared__ int s_nf;
     const int TT = g.T * g.T;
     const int sh = pack_frac_bits<R>(lb) + 1;         // position of the cell bits
-    int* hist = sm;            // per-cell counts
-    int* cst = sm + TT;        // per-cell start offsets, then scatter cursors
+    int* cnt = sm;             // per-cell counts, then ranks while placing
+    int* cinfo = sm + TT;      // per cell: F(c) | (first tail entry) << 16   (both < 2^16: cap <= 16384)
     const int n_items = flags[1];
     for (int e = flags[2] + blockIdx.x * blockDim.x + threadIdx.x; e < nvis; e += gridDim.x * blockDim.x)
         pos2[e] = -1;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {     // uniform across the workgroup
         const int4 it = items[item];
-        for (int c = threadIdx.x; c < TT; c += blockDim.x) hist[c] = 0;
-        for (int q = threadIdx.x; q < kMaxCap / kPiece + 1; q += blockDim.x) qcnt[q] = 0;
+        for (int c = threadIdx.x; c < TT; c += blockDim.x) cnt[c] = 0;
         if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
         __syncthreads();
         for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
             const typename Pack<R>::T2 r = off0[it.y + e];
-            atomicAdd(&hist[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
+            atomicAdd(&cnt[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
         }
         __syncthreads();
+        // full pieces: exclusive prefix F over cells (each thread a run of cells); tails counted by length
         const int seg = (TT + blockDim.x - 1) / blockDim.x;
         const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
-        int sum = 0;
-        for (int c = c0; c < c1; ++c) sum += hist[c];
-        part[threadIdx.x] = sum;
+        int fsum = 0;
+        for (int c = c0; c < c1; ++c) {
+            const int n = cnt[c];
+            fsum += n / kPiece;
+            if (n % kPiece) atomicAdd(&lcnt[n % kPiece], 1);
+        }
+        part[threadIdx.x] = fsum;
         __syncthreads();
         for (int o = 1; o < 256; o <<= 1) {            // inclusive scan of the 256 partial sums
             const int v = (threadIdx.x >= o) ? part[threadIdx.x - o] : 0;
@@ -512,57 +519,55 @@ __global__ __launch_bounds__(256) void k_plan_sort_items(PlanGeom g, int4* __res
             part[threadIdx.x] += v;
             __syncthreads();
         }
-        int run = part[threadIdx.x] - sum;
+        int F = part[threadIdx.x] - fsum;
         for (int c = c0; c < c1; ++c) {
-            cst[c] = run;
-            run += hist[c];
-            const int f = hist[c] / kPiece, t = hist[c] % kPiece;
-            for (int q = 0; q < f; ++q) atomicAdd(&qcnt[q], 1);
-            if (t) atomicAdd(&lcnt[t], 1);
+            cinfo[c] = F;
+            F += cnt[c] / kPiece;
         }
+        if (threadIdx.x == blockDim.x - 1) s_nf = part[threadIdx.x];
         __syncthreads();
-        if (threadIdx.x < 64) {                          // piece slots: full by level, then tails by length
-            // Wave 0: each lane owns a run of levels (then one tail length, longest first) and the
-            // wave scans the run totals.
-            constexpr int kLevels = kMaxCap / kPiece + 1;
-            constexpr int kPer = (kLevels + 63) / 64;
+        if (threadIdx.x < 64) {                          // tail slots and entries, longest first
+            const int nf = s_nf;
             const int ln = threadIdx.x;
-            int run = 0;
-            for (int i = 0; i < kPer; ++i) {
-                const int q = ln * kPer + i;
-                if (q < kLevels) run += qcnt[q];
+            const int t = kPiece - 1 - ln;               // lengths 31 .. 1 on lanes 0 .. 30
+            const int n = (ln < kPiece - 1) ? lcnt[t] : 0;
+            const int inc_n = wave_incl_sum(n);
+            const int inc_e = wave_incl_sum(n * t);
+            if (ln < kPiece - 1) {
+                lfirst[t] = nf + inc_n - n;
+                lcnt[t] = nf + inc_n - n;
+                lbase[t] = nf * kPiece + inc_e - n * t;
             }
-            const int tail = (ln < kPiece - 1) ? lcnt[kPiece - 1 - ln] : 0;   // lengths 31 .. 1
-            const int inc_q = wave_incl_sum(run);
-            const int total_q = __shfl(inc_q, 63, 64);
-            int a = inc_q - run;
-            for (int i = 0; i < kPer; ++i) {
-                const int q = ln * kPer + i;
-                if (q < kLevels) {
-                    const int x = qcnt[q];
-                    qcnt[q] = a;
-                    a += x;
-                }
-            }
-            const int inc_t = wave_incl_sum(tail);
-            if (ln < kPiece - 1) lcnt[kPiece - 1 - ln] = total_q + inc_t - tail;
-            if (ln == 63) items[item].w = total_q + inc_t;
+            if (ln == 63) items[item].w = nf + inc_n;
         }
         __syncthreads();
         for (int c = c0; c < c1; ++c) {
-            const int n = hist[c];
+            const int n = cnt[c];
+            cnt[c] = 0;                                  // ranks while placing
             if (!n) continue;
             const int f = n / kPiece, t = n % kPiece;
-            const int start = it.y + cst[c];
             const int lc = ((c / g.T) << 8) | (c % g.T);
+            const int Fc = cinfo[c];
             for (int q = 0; q < f; ++q)
-                pieces[it.y + atomicAdd(&qcnt[q], 1)] = make_int2(start + q * kPiece, kPiece | (lc << 16));
-            if (t) pieces[it.y + atomicAdd(&lcnt[t], 1)] = make_int2(start + f * kPiece, t | (lc << 16));
+                pieces[it.y + Fc + q] = make_int2(it.y + (Fc + q) * kPiece, kPiece | (lc << 16));
+            if (t) {
+                const int slot = atomicAdd(&lcnt[t], 1);
+                const int first = lbase[t] + t * (slot - lfirst[t]);
+                pieces[it.y + slot] = make_int2(it.y + first, t | (lc << 16));
+                cinfo[c] = Fc | (first << 16);
+            }
         }
         __syncthreads();
+        const int nf = s_nf;
         for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
             const typename Pack<R>::T2 r = off0[it.y + e];
-            const int dst = it.y + atomicAdd(&cst[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
+            const int c = static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh);
+            const int rank = atomicAdd(&cnt[c], 1);
+            const int ci = cinfo[c];
+            const int Fc = ci & 0xffff;
+            const int f = ((c + 1 < TT) ? (cinfo[c + 1] & 0xffff) : nf) - Fc;
+            const int pos = rank < f * kPiece ? Fc * kPiece + rank : (ci >> 16) + rank - f * kPiece;
+            const int dst = it.y + pos;
             off[dst] = r;
             pos2[it.y + e] = dst;
         }
@@ -865,7 +870,9 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
         constexpr int kB = 4;                               // entries whose loads are issued together
         const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
         for (int rd = 0; rd < rounds; ++rd) {               // uniform across the workgroup
-            const int p = rd * blockDim.x + threadIdx.x;
+            // consecutive pieces go to different waves (a dense cell's full pieces are neighbours, and
+            // lanes of one wave sharing a cell flush in turns)
+            const int p = rd * blockDim.x + (threadIdx.x & 63) * (blockDim.x >> 6) + (threadIdx.x >> 6);
             const bool have = p < it.w;
             int2 pc = make_int2(0, 0);
             if (have) pc = a.pieces[it.y + p];
