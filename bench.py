@@ -78,7 +78,8 @@ def load_traffic(kernel: str, nvis: int):
 # Library trace names -> device kernel symbols (rocprofv3 names them by symbol).
 TRACE_TO_SYMBOL = {
     "plan_count": "k_plan_count", "plan_colscan": "k_plan_colscan", "plan_scan": "k_plan_scan",
-    "plan_scatter": "k_plan_scatter", "plan_sort_items": "k_plan_sort_items", "plan_compose": "k_plan_compose",
+    "plan_scatter": "k_plan_scatter", "plan_place": "k_plan_place", "plan_sort_items": "k_plan_sort_items",
+    "plan_compose": "k_plan_compose",
     "permute_in": "k_permute_in", "grid_items": "k_grid_items", "assemble": "k_assemble",
     "degrid_items": "k_degrid_items", "permute_out": "k_permute_out",
 }

@@ -56,7 +56,7 @@ struct lmg_plan {
     int4* items = nullptr;
     int* inv0 = nullptr;           // caller index -> tile-order position
     void* off0 = nullptr;          // packed offsets, by tile-order position
-    void* off = nullptr;           // packed offsets, by entry (cell order within items)
+    void* off = nullptr;           // packed offsets, by entry (piece order within items)
     int* pos2 = nullptr;           // tile-order position -> entry (-1: dropped)
     int* inv = nullptr;            // caller index -> entry (-1: dropped)
     int2* pieces = nullptr;
@@ -615,8 +615,13 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     }
     {
         TraceScope ts("plan_scatter", s);
+        // packed offsets by caller index go to `off` for now (the item sort overwrites it)
         LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, p->blocks, p->nblocks, p->g, p->tile_start, p->blockhist,
-                                    delta_low(table->W), p->lb, p->inv0, p->off0, s));
+                                    delta_low(table->W), p->lb, p->inv0, p->off, s));
+    }
+    {
+        TraceScope ts("plan_place", s);
+        LMG_HIP(launch_plan_place(prec == LMG_F64, p->inv0, p->off, p->flags, nvis, p->off0, s));
     }
     {
         TraceScope ts("plan_sort_items", s);

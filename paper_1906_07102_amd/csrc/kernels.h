@@ -92,9 +92,13 @@ hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* cha
                                hipStream_t s);
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
                             int* flags, int cap, hipStream_t s);
+// inv0[k] = tile-order position, offk[k] = packed offsets (both by caller index).
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* off0,
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* offk,
                                hipStream_t s);
+// off0[inv0[k]] = offk[k] for the valid visibilities (flags[2] of them).
+hipError_t launch_plan_place(bool f64, const int* inv0, const void* offk, const int* flags, int64_t nvis, void* off0,
+                             hipStream_t s);
 hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags, int nvis,
                             int lb, const void* off0, void* off, int* pos2, int2* pieces, hipStream_t s);
 hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s);

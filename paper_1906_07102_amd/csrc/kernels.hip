@@ -417,14 +417,17 @@ __global__ __launch_bounds__(1024) void k_plan_scan(PlanGeom g, const int* __res
 }
 
 // Pass 3: give each visibility its tile-order position (inv0, by caller
-// index) and store its packed offsets there (off0).
+// index) and its packed offsets (offk, by caller index): both writes are
+// coalesced. The scattered store of the offsets into tile order is a pass of
+// its own (k_plan_place): here each XCD runs 32 plan blocks, that is 32
+// time windows, at once, and their partly written lines would overflow L2.
 template <typename R>
 __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __restrict__ uv,
                                                                const int4* __restrict__ blocks, int nb, PlanGeom g,
                                                                const int* __restrict__ tile_start,
                                                                const int* __restrict__ blockhist, double dlo, int lb,
                                                                int* __restrict__ inv0,
-                                                               typename Pack<R>::T2* __restrict__ off0) {
+                                                               typename Pack<R>::T2* __restrict__ offk) {
     extern __shared__ int cur[];
     const int hs = g.ntiles + 1;
     const int chunk = xcd_chunk(blockIdx.x, nb);
@@ -454,13 +457,28 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
                 typename Pack<R>::T2 o;
                 o.x = pack_axis<R>(cu % g.T, du, dlo, lb);
                 o.y = pack_axis<R>(cv % g.T, dv, dlo, lb);
-                off0[dst] = o;
+                offk[k] = o;
                 inv0[k] = dst;
             } else {
                 inv0[k] = atomicAdd(&cur[g.ntiles], 1);            // dropped: a position after the valid ones
             }
         }
     }
+}
+
+// Pass 3b: packed offsets into tile order, off0[inv0[k]] = offk[k] for the
+// valid visibilities (flags[2] of them; dropped ones sit above). Consecutive
+// workgroups take consecutive indices on one XCD, so its L2 sees one window
+// of the caller order at a time and merges the scattered writes into lines.
+template <typename R>
+__global__ __launch_bounds__(256) void k_plan_place(const int* __restrict__ inv0,
+                                                    const typename Pack<R>::T2* __restrict__ offk,
+                                                    const int* __restrict__ flags, int64_t nvis,
+                                                    typename Pack<R>::T2* __restrict__ off0) {
+    const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
+    if (k >= nvis) return;
+    const int d = inv0[k];
+    if (d < flags[2]) off0[d] = offk[k];
 }
 
 // Pass 4 (workgroups loop over items): order the item's visibilities into
@@ -1340,18 +1358,31 @@ int packed_frac_bits(bool f64, int lb) {
 }
 
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* off0,
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* offk,
                                hipStream_t s) {
     if (nb == 0) return hipSuccess;
     const size_t shm = (g.ntiles + 1) * sizeof(int);
     if (f64)
         hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), shm, s,
                            reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
-                           inv0, reinterpret_cast<ulonglong2*>(off0));
+                           inv0, reinterpret_cast<ulonglong2*>(offk));
     else
         hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), shm, s,
                            reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
-                           inv0, reinterpret_cast<uint2*>(off0));
+                           inv0, reinterpret_cast<uint2*>(offk));
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_place(bool f64, const int* inv0, const void* offk, const int* flags, int64_t nvis, void* off0,
+                             hipStream_t s) {
+    if (nvis == 0) return hipSuccess;
+    const unsigned nb = static_cast<unsigned>((nvis + 255) / 256);
+    if (f64)
+        hipLaunchKernelGGL(dev::k_plan_place<double>, dim3(nb), dim3(256), 0, s, inv0,
+                           reinterpret_cast<const ulonglong2*>(offk), flags, nvis, reinterpret_cast<ulonglong2*>(off0));
+    else
+        hipLaunchKernelGGL(dev::k_plan_place<float>, dim3(nb), dim3(256), 0, s, inv0,
+                           reinterpret_cast<const uint2*>(offk), flags, nvis, reinterpret_cast<uint2*>(off0));
     return hipGetLastError();
 }
 
