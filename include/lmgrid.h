@@ -92,6 +92,23 @@ lmg_status lmg_table_create_from_h(int W, double x0, int table_size, int degree,
 lmg_status lmg_table_create_from_nodes(int W, double x0, int table_size, int degree,
                                        const double* h_coarse, const double* nodes, lmg_table** out);
 
+/* Direct calculation (the paper's Sec. 6 alternative to a look-up table):
+ * a table object with the same W, x0 and h as `from` whose gridding and
+ * degridding kernels evaluate the exact kernel C(t_j - delta) = [A^{-1}
+ * B(delta)]_j (Eq. 18) at each visibility's offset instead of interpolating
+ * nodes, so no table error enters. The solve is expanded once on the host
+ * over the 33 h samples (App. A), c_j(delta) = sum_i P_ji cos(i theta) + Q_ji
+ * sin(i theta) with theta = 2 pi delta x0 / 32, and the device evaluates
+ * that sum in FP64 in every precision mode (about 1,300 FP64 operations per
+ * visibility: an arithmetic-bound variant). The grid and visibilities keep
+ * the plan's precision. `from` is not modified and may be destroyed first.
+ * Plans take the table like any other; the FFT, correction and crop are
+ * unchanged. Errors: LMG_EINVAL (NULL argument, singular normal matrix). */
+lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out);
+
+/* *direct = 1 for a table made by lmg_table_create_direct, else 0. */
+lmg_status lmg_table_is_direct(const lmg_table* t, int* direct);
+
 /* Parameters of a table. Any output pointer may be NULL. */
 lmg_status lmg_table_info(const lmg_table* t, int* W, double* x0, int* Ms, int* degree,
                           double* integrated_misfit);

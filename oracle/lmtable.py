@@ -255,6 +255,21 @@ class Table:
         return interpolate(self.nodes, self.W, self.Ms, self.degree, delta).T
 
 
+@dataclass(frozen=True)
+class ExactKernel:
+    """Direct calculation of the weights (Sec. 6): the exact kernel at every offset, no table.
+
+    Same interface as :class:`Table`; each call solves Eq. (18) at the given
+    offsets with :func:`kernel_from_h`.
+    """
+    W: int
+    x0: float
+    h: np.ndarray
+
+    def weights(self, delta) -> np.ndarray:
+        return kernel_from_h(self.h, self.W, self.x0, delta).T
+
+
 def interpolate(nodes: np.ndarray, W: int, Ms: int, degree: int, delta) -> np.ndarray:
     """Kernel values from the table (App. F), W x n.
 

@@ -73,6 +73,8 @@ def load():
         "lmg_table_create": (I, [I, D, I, I, ctypes.POINTER(P)]),
         "lmg_table_create_from_h": (I, [I, D, I, I, PD, ctypes.POINTER(P)]),
         "lmg_table_create_from_nodes": (I, [I, D, I, I, PD, PD, ctypes.POINTER(P)]),
+        "lmg_table_create_direct": (I, [P, ctypes.POINTER(P)]),
+        "lmg_table_is_direct": (I, [P, PI]),
         "lmg_table_info": (I, [P, PI, PD, PI, PI, PD]),
         "lmg_table_export": (I, [P, PD, PD]),
         "lmg_table_kernel": (I, [P, I, PD, PD]),
@@ -142,6 +144,9 @@ class Table:
                                         ctypes.byref(deg), ctypes.byref(E)), "lmg_table_info")
         self.W, self.x0, self.Ms, self.degree, self.integrated_misfit = W.value, x0.value, Ms.value, deg.value, E.value
         self.table_size = self.W * self.Ms
+        d = ctypes.c_int()
+        _check(self._lib.lmg_table_is_direct(self._h, ctypes.byref(d)), "lmg_table_is_direct")
+        self.direct = bool(d.value)
 
     @classmethod
     def create(cls, W: int, x0: float, table_size: int, degree: int = 3) -> "Table":
@@ -170,6 +175,12 @@ class Table:
         _check(load().lmg_table_create_from_nodes(W, x0, table_size, degree, _dptr(h), _dptr(nodes),
                                                   ctypes.byref(out)), "lmg_table_create_from_nodes")
         return cls(out)
+
+    def direct_calculation(self) -> "Table":
+        """The same kernel evaluated exactly at each visibility's offset (no table), lmg_table_create_direct."""
+        out = ctypes.c_void_p()
+        _check(self._lib.lmg_table_create_direct(self._h, ctypes.byref(out)), "lmg_table_create_direct")
+        return Table(out)
 
     def export(self):
         h = np.zeros(NG + 1)

@@ -261,6 +261,21 @@ lmg_status upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     return LMG_OK;
 }
 
+// The coefficients a plan uploads: the interval polynomials of a table in
+// the plan's precision, or for a direct table the FP64 expansion (pq).
+const void* coef_host(const lmg_table* t, lmg_precision prec) {
+    if (t->direct) return t->pq.data();
+    return prec == LMG_F64 ? static_cast<const void*>(t->coef64.data()) : static_cast<const void*>(t->coef32.data());
+}
+size_t coef_bytes(const lmg_table* t, lmg_precision prec) {
+    if (t->direct) return t->pq.size() * sizeof(double);
+    return prec == LMG_F64 ? t->coef64.size() * sizeof(double) : t->coef32.size() * sizeof(float);
+}
+// Table intervals the kernels stage in LDS (-1: none, for a direct table) and the
+// kernels' table mode (-1: direct).
+int staged_ms(const lmg_table* t) { return t->direct ? -1 : t->Ms; }
+int kernel_degree(const lmg_table* t) { return t->direct ? -1 : t->degree; }
+
 // The plan constants of (table, N, precision) in pinned host memory, built on
 // first use: copies from it are asynchronous. nullptr if pinned memory is
 // unavailable (the caller then uploads from pageable memory).
@@ -271,7 +286,7 @@ const lmg_table::Pinned* pinned_constants(const lmg_table* t, int N, lmg_precisi
     if (it != t->pinned.end()) return it->second.host ? &it->second : nullptr;
     lmg_table::Pinned pc;
     const bool f64 = prec == LMG_F64;
-    pc.coef_bytes = f64 ? t->coef64.size() * 8 : t->coef32.size() * 4;
+    pc.coef_bytes = coef_bytes(t, prec);
     pc.twiddle_bytes = 2 * static_cast<size_t>(N) * (f64 ? 8 : 4);
     pc.hpix_bytes = static_cast<size_t>(N) * (f64 ? 8 : 4);
     pc.coef = 0;
@@ -285,12 +300,11 @@ const lmg_table::Pinned* pinned_constants(const lmg_table* t, int N, lmg_precisi
         return nullptr;
     }
     char* b = static_cast<char*>(pc.host);
+    std::memcpy(b + pc.coef, coef_host(t, prec), pc.coef_bytes);
     if (f64) {
-        std::memcpy(b + pc.coef, t->coef64.data(), pc.coef_bytes);
         std::memcpy(b + pc.twiddle, twiddles_f64(N).data(), pc.twiddle_bytes);
         std::memcpy(b + pc.hpix, h.data(), pc.hpix_bytes);
     } else {
-        std::memcpy(b + pc.coef, t->coef32.data(), pc.coef_bytes);
         std::memcpy(b + pc.twiddle, twiddles_f32(N).data(), pc.twiddle_bytes);
         float* hf = reinterpret_cast<float*>(b + pc.hpix);
         for (int i = 0; i < N; ++i) hf[i] = static_cast<float>(h[i]);
@@ -428,7 +442,7 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
         LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vs, s));
     }
     GridArgs a{};
-    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = staged_ms(t); a.degree = kernel_degree(t);
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.vis = vs; a.patches = patches; a.counter = counters;
@@ -456,7 +470,7 @@ lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* 
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters + 1, 1, s));
     DegridArgs a{};
-    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = t->Ms; a.degree = t->degree;
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = staged_ms(t); a.degree = kernel_degree(t);
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
@@ -505,11 +519,11 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     const int64_t nvis = offsets[nchan];
     if (nvis < 0 || nvis > INT32_MAX || (nvis > 0 && !uv)) return LMG_EINVAL;
     if (tile != 0 && (!is_pow2(tile) || tile < 8 || tile > 128 || tile > N || N / tile > 128)) return LMG_EINVAL;
-    const size_t tab_bytes = (prec == LMG_F64 ? table->coef64.size() * 8 : table->coef32.size() * 4);
+    const size_t tab_bytes = coef_bytes(table, prec);
     if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
-    const int T = tile ? tile : fit_tile(choose_tile(N, prec), N, prec, table->W, table->Ms);
-    const int waves = fit_waves(T, prec, table->W, table->Ms);
-    if (grid_lds_bytes(prec, table->W, T, table->Ms, waves) > kMaxDynLds) return LMG_ENOTSUP;
+    const int T = tile ? tile : fit_tile(choose_tile(N, prec), N, prec, table->W, staged_ms(table));
+    const int waves = fit_waves(T, prec, table->W, staged_ms(table));
+    if (grid_lds_bytes(prec, table->W, T, staged_ms(table), waves) > kMaxDynLds) return LMG_ENOTSUP;
     const int cap = choose_cap();
     const Layout L = plan_layout(N, nvis, prec, cap, nchan);
     if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
@@ -573,11 +587,11 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
         if (upload(p->twiddle, b + pc->twiddle, pc->twiddle_bytes, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->hpix, b + pc->hpix, pc->hpix_bytes, s) != LMG_OK) return LMG_EHIP;
     } else if (prec == LMG_F64) {
-        if (upload(p->coef, table->coef64.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->coef, coef_host(table, prec), tab_bytes, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->twiddle, twiddles_f64(N).data(), 2 * sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->hpix, h.data(), sizeof(double) * N, s) != LMG_OK) return LMG_EHIP;
     } else {
-        if (upload(p->coef, table->coef32.data(), tab_bytes, s) != LMG_OK) return LMG_EHIP;
+        if (upload(p->coef, coef_host(table, prec), tab_bytes, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->twiddle, twiddles_f32(N).data(), 2 * sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
         if (upload(p->hpix, hf.data(), sizeof(float) * N, s) != LMG_OK) return LMG_EHIP;
     }

@@ -32,6 +32,9 @@ struct PlanGeom {
     double ref;   // offset of the reference tap from the first tap
 };
 
+// Ms: table intervals staged in LDS; degree: interpolation degree. A direct
+// table has Ms = -1 (nothing staged) and degree = -1, and coef holds its FP64
+// expansion (the weights are computed per visibility).
 struct GridArgs {
     int N, W, T, ntx, Ms, degree;
     const int* n_items;    // device: number of work items (written by the plan)
@@ -41,7 +44,7 @@ struct GridArgs {
     const int4* items;     // (tile, first position, count, pieces)
     const int2* pieces;    // (first entry, length | cell << 16)
     const void* off;       // packed offsets (uint2 or ulonglong2), entry order
-    const void* coef;      // coefficient table, float or double
+    const void* coef;      // coefficient table, float or double; FP64 expansion for a direct table
     const void* vis;       // complex, entry order, weights applied
     void* patches;         // n_items patches of (T + W - 1)^2 cells
     int* counter;          // work-item counter, zero at launch

@@ -76,6 +76,42 @@ __device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int d
 }
 
 
+// Direct calculation of the W tap weights (no table): the exact kernel
+// C(t_j - delta) = [A^{-1} B(delta)]_j (Eq. 18), expanded on the host over the
+// 33 h samples as c_j = sum_i P_ji cos(i theta) + Q_ji sin(i theta) with
+// theta = 2 pi delta x0 / 32. pq holds P (W x 33), Q (W x 33), then 2 pi x0 /
+// 32. The offset comes back exactly from the packed word (q 2^-F above the
+// interval's low end); cos(i theta), sin(i theta) follow by the angle-sum
+// recurrence from one sincos. FP64 throughout; the coefficient index is
+// uniform across the wave, so its loads are scalar.
+template <typename R, int W, typename P>
+__device__ __forceinline__ void weights_direct(const double* pq_global, P p, int F, R* out) {
+    // read through the constant address space: the coefficients are never written while a kernel
+    // runs, and their index is uniform, so they load into scalar registers
+    using cdouble = const __attribute__((address_space(4))) double;
+    cdouble* pq = (cdouble*)pq_global;                            // address-space cast
+    constexpr int NI = 33;
+    constexpr double dlo = (W & 1) ? -0.5 : 0.0;
+    const unsigned long long q = static_cast<unsigned long long>(p) & ((2ull << F) - 1);
+    const double delta = dlo + ldexp(static_cast<double>(q), -F);
+    double s1, c1;
+    sincos(pq[2 * W * NI] * delta, &s1, &c1);
+    double acc[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) acc[j] = pq[j * NI];            // i = 0: cos 0 = 1, sin 0 = 0
+    double ci = 1.0, si = 0.0;
+#pragma unroll 4
+    for (int i = 1; i < NI; ++i) {
+        const double cn = ci * c1 - si * s1;
+        si = si * c1 + ci * s1;
+        ci = cn;
+#pragma unroll
+        for (int j = 0; j < W; ++j) acc[j] = fma(pq[j * NI + i], ci, fma(pq[(W + j) * NI + i], si, acc[j]));
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) out[j] = static_cast<R>(acc[j]);
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
 // Streaming kernels map workgroup b to chunk xcd_chunk(b, nb), so that every
 // XCD walks one contiguous run of chunks and data written or read by
@@ -854,7 +890,7 @@ __device__ __forceinline__ void flush_rows(typename Acc::Cell* patch, unsigned c
 // (a.counter, zero at launch) until none are left, so the table is staged
 // once per workgroup and uneven items (many channels of very different
 // sizes) balance dynamically.
-template <typename R, typename Acc, int W>
+template <typename R, typename Acc, int W, bool kDirect>
 __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
@@ -911,8 +947,13 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
                     for (int u = 0; u < kB; ++u) {
                         if (j0 + u >= len) break;
                         R cu[W], cv[W];
-                        weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
-                        weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
+                        if constexpr (kDirect) {
+                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].x, a.F, cu);
+                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].y, a.F, cv);
+                        } else {
+                            weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
+                            weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
+                        }
 #pragma unroll
                         for (int r = 0; r < RG; ++r) {
                             if (r0 + r >= W) break;
@@ -1003,7 +1044,7 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
 // offset word (bits above F). (Caching a lane's footprint in registers over
 // a run of its visibilities measured slower: the register cost lowers
 // occupancy more than the LDS reads it saves.)
-template <typename R, int W>
+template <typename R, int W, bool kDirect>
 __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
@@ -1039,8 +1080,13 @@ __global__ __launch_bounds__(256) void k_degrid_items(DegridArgs a) {
             const PT2 d = off[e];
             const int cu = static_cast<int>(d.x >> cshift), cv = static_cast<int>(d.y >> cshift);
             R wu[W], wv[W];
-            weights<R, W>(tab, a.Ms, a.degree, d.x, a.F, wu);
-            weights<R, W>(tab, a.Ms, a.degree, d.y, a.F, wv);
+            if constexpr (kDirect) {
+                weights_direct<R, W>(static_cast<const double*>(a.coef), d.x, a.F, wu);
+                weights_direct<R, W>(static_cast<const double*>(a.coef), d.y, a.F, wv);
+            } else {
+                weights<R, W>(tab, a.Ms, a.degree, d.x, a.F, wu);
+                weights<R, W>(tab, a.Ms, a.degree, d.y, a.F, wv);
+            }
             const VT* row = patch + cv * P + cu;
             R accr = 0, acci = 0;
 #pragma unroll
@@ -1278,35 +1324,36 @@ int resident_blocks(size_t shm) {
     const int by_lds = shm > 0 ? static_cast<int>((160 * 1024) / shm) : 8;
     return cus[dev] * std::max(1, std::min(8, by_lds));
 }
-template <typename R, typename Acc, int W>
+template <typename R, typename Acc, int W, bool kDirect>
 hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
     const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 1) * a.waves;
-    const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W>);
+    const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W, kDirect>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
     const int nb = std::min(a.max_items, resident_blocks(shm));
-    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W>), dim3(nb), dim3(64 * a.waves), shm, s, a);
+    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W, kDirect>), dim3(nb), dim3(64 * a.waves), shm, s, a);
     return hipGetLastError();
 }
-template <typename R, int W>
+template <typename R, int W, bool kDirect>
 hipError_t launch_degrid_w(const DegridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
     const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
     const size_t shm = tab + static_cast<size_t>(P) * P * sizeof(typename dev::C2<R>::T);
-    const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W>);
+    const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W, kDirect>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
     const int nb = std::min(a.max_items, resident_blocks(shm));
-    hipLaunchKernelGGL((dev::k_degrid_items<R, W>), dim3(nb), dim3(256), shm, s, a);
+    hipLaunchKernelGGL((dev::k_degrid_items<R, W, kDirect>), dim3(nb), dim3(256), shm, s, a);
     return hipGetLastError();
 }
 
 template <typename R, typename Acc>
 hipError_t dispatch_grid(const GridArgs& a, hipStream_t s) {
     switch (a.W) {
-#define LMG_CASE(w) case w: return launch_grid_w<R, Acc, w>(a, s);
+#define LMG_CASE(w) \
+    case w: return a.degree < 0 ? launch_grid_w<R, Acc, w, true>(a, s) : launch_grid_w<R, Acc, w, false>(a, s);
         LMG_CASE(1) LMG_CASE(2) LMG_CASE(3) LMG_CASE(4) LMG_CASE(5) LMG_CASE(6) LMG_CASE(7) LMG_CASE(8)
         LMG_CASE(9) LMG_CASE(10) LMG_CASE(11) LMG_CASE(12) LMG_CASE(13) LMG_CASE(14) LMG_CASE(15) LMG_CASE(16)
 #undef LMG_CASE
@@ -1316,7 +1363,8 @@ hipError_t dispatch_grid(const GridArgs& a, hipStream_t s) {
 template <typename R>
 hipError_t dispatch_degrid(const DegridArgs& a, hipStream_t s) {
     switch (a.W) {
-#define LMG_CASE(w) case w: return launch_degrid_w<R, w>(a, s);
+#define LMG_CASE(w) \
+    case w: return a.degree < 0 ? launch_degrid_w<R, w, true>(a, s) : launch_degrid_w<R, w, false>(a, s);
         LMG_CASE(1) LMG_CASE(2) LMG_CASE(3) LMG_CASE(4) LMG_CASE(5) LMG_CASE(6) LMG_CASE(7) LMG_CASE(8)
         LMG_CASE(9) LMG_CASE(10) LMG_CASE(11) LMG_CASE(12) LMG_CASE(13) LMG_CASE(14) LMG_CASE(15) LMG_CASE(16)
 #undef LMG_CASE

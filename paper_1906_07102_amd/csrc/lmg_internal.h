@@ -33,6 +33,12 @@ struct lmg_table {
     // stored at [(k * W + j) * 4 + s]. Degree 0 stores the node in c0.
     std::vector<float> coef32;
     std::vector<double> coef64;
+    // Direct calculation (no table): the kernels evaluate the exact kernel at
+    // each offset from pq = P (W x (kNg+1)), Q (W x (kNg+1)), 2 pi x0 / kNg,
+    // c_j(delta) = sum_i P_ji cos(i theta) + Q_ji sin(i theta), theta =
+    // 2 pi delta x0 / kNg; FP64 in every precision mode.
+    bool direct = false;
+    std::vector<double> pq;
     // Correction vectors already computed, by grid size.
     mutable std::mutex cache_mu;
     mutable std::map<int, std::vector<double>> hpix_cache;

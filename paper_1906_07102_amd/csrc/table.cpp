@@ -265,6 +265,38 @@ bool exact_kernel(int W, double x0, const std::vector<double>& h, const double* 
     return true;
 }
 
+// Expansion of the exact kernel over the h samples (Eq. 18 with Eq. 19's
+// quadrature): B_r(delta) = 2 sum_i tau_i h_i cos(2 pi (t_r - delta) x_i)
+// splits by the angle-difference identity into cos(2 pi t_r x_i) cos(2 pi
+// delta x_i) + sin(2 pi t_r x_i) sin(2 pi delta x_i), so C = A^{-1} B is
+// sum_i P_i cos(i theta) + Q_i sin(i theta) with theta = 2 pi delta x0 / N_g,
+// P_i = A^{-1} (2 tau_i h_i cos(2 pi t x_i)), Q_i = A^{-1} (2 tau_i h_i sin(2 pi t x_i)).
+bool direct_coefficients(int W, double x0, const std::vector<double>& h, std::vector<double>& pq) {
+    Problem P(W, x0);
+    std::vector<double> A;
+    P.normal_matrix(h.data(), A);
+    if (!cholesky(A, W)) return false;
+    const double ref = tap_reference(W);
+    const int ni = kNg + 1;
+    pq.assign(2 * static_cast<size_t>(W) * ni + 1, 0.0);
+    std::vector<double> c(W), sn(W);
+    for (int i = 0; i < ni; ++i) {
+        for (int r = 0; r < W; ++r) {
+            const double ph = 2 * kPi * (r - ref) * P.x[i];
+            c[r] = 2.0 * P.tau[i] * h[i] * std::cos(ph);
+            sn[r] = 2.0 * P.tau[i] * h[i] * std::sin(ph);
+        }
+        cholesky_solve(A, W, c.data());
+        cholesky_solve(A, W, sn.data());
+        for (int j = 0; j < W; ++j) {
+            pq[static_cast<size_t>(j) * ni + i] = c[j];
+            pq[static_cast<size_t>(W + j) * ni + i] = sn[j];
+        }
+    }
+    pq[2 * static_cast<size_t>(W) * ni] = 2 * kPi * x0 / kNg;
+    return true;
+}
+
 bool valid_params(int W, double x0, int table_size, int degree) {
     return W >= 1 && W <= kMaxW && x0 > 0.0 && x0 <= 0.5 && table_size >= W && degree >= 0 && degree <= 3 &&
            (table_size / W) >= 2;
@@ -443,6 +475,31 @@ lmg_status lmg_table_create_from_nodes(int W, double x0, int table_size, int deg
     return LMG_OK;
 }
 
+lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out) {
+    if (!from || !out) return LMG_EINVAL;
+    std::unique_ptr<lmg_table> t(new (std::nothrow) lmg_table);
+    if (!t) return LMG_EINVAL;
+    t->W = from->W;
+    t->x0 = from->x0;
+    t->Ms = from->Ms;
+    t->degree = from->degree;
+    t->E = from->E;
+    t->h = from->h;
+    t->nodes = from->nodes;
+    t->coef32 = from->coef32;
+    t->coef64 = from->coef64;
+    t->direct = true;
+    if (!direct_coefficients(t->W, t->x0, t->h, t->pq)) return LMG_EINVAL;
+    *out = t.release();
+    return LMG_OK;
+}
+
+lmg_status lmg_table_is_direct(const lmg_table* t, int* direct) {
+    if (!t || !direct) return LMG_EINVAL;
+    *direct = t->direct ? 1 : 0;
+    return LMG_OK;
+}
+
 lmg_status lmg_table_info(const lmg_table* t, int* W, double* x0, int* Ms, int* degree, double* E) {
     if (!t) return LMG_EINVAL;
     if (W) *W = t->W;
@@ -508,7 +565,11 @@ lmg_status lmg_map_error(const lmg_table* t, int n, const double* x, double* ell
             tw.push_back(gw[q]);
         }
     std::vector<double> tv(td.size() * t->W);
-    for (size_t q = 0; q < td.size(); ++q) table_weights(t, td[q], &tv[q * t->W]);
+    if (t->direct) {                      // no table: the kernels evaluate the exact kernel
+        if (!exact_kernel(t->W, t->x0, t->h, td.data(), static_cast<int>(td.size()), tv.data())) return LMG_EINVAL;
+    } else {
+        for (size_t q = 0; q < td.size(); ++q) table_weights(t, td[q], &tv[q * t->W]);
+    }
     for (int i = 0; i < n; ++i) {
         double c, D, e;
         nu_integrals(t->W, qd, qw, kv, x[i], 0.0, false, &c, &D, nullptr);

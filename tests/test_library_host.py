@@ -88,6 +88,29 @@ def test_from_nodes_roundtrip():
     assert t.Ms == 60 and t.degree == 1 and t.W == 5
 
 
+def test_direct_calculation_table():
+    """lmg_table_create_direct: same W, x0 and h; no table error in the map error; NULL arguments rejected."""
+    otab, h = lt.make_table(7, 0.25, 300, 3)
+    t = lmg.Table.from_nodes(7, 0.25, 300, 3, h, otab.nodes)
+    d = t.direct_calculation()
+    assert d.direct and not t.direct
+    assert (d.W, d.x0, d.Ms, d.degree) == (t.W, t.x0, t.Ms, t.degree)
+    np.testing.assert_array_equal(d.export()[0], h)
+    x = np.linspace(0.0, 0.25, 9)
+    ell_exact, ell_direct = d.map_error(x)
+    # the two columns integrate over nu with different rules (64 Gauss-Legendre points, 8 per table interval),
+    # and l(x) ~ 1e-14 is the small difference of O(1) terms: they agree to about 1e-8
+    np.testing.assert_allclose(ell_direct, ell_exact, rtol=1e-6, atol=1e-30)
+    _, ell_table = t.map_error(x)
+    assert np.max(ell_table) > np.max(ell_direct)        # the table adds its interpolation error
+    lib = lmg.load()
+    out = ctypes.c_void_p()
+    assert lib.lmg_table_create_direct(None, ctypes.byref(out)) == -1
+    assert lib.lmg_table_create_direct(t.handle, None) == -1
+    flag = ctypes.c_int(7)
+    assert lib.lmg_table_is_direct(None, ctypes.byref(flag)) == -1
+
+
 @pytest.mark.parametrize("args", [(0, 0.25, 300, 3), (17, 0.25, 300, 3), (7, 0.0, 300, 3), (7, 0.6, 300, 3),
                                   (7, 0.25, 6, 3), (7, 0.25, 300, 4), (7, 0.25, 300, -1)])
 def test_table_invalid_arguments(args):
