@@ -282,6 +282,55 @@ def precision_study(lmg, case, uv, vis64, reps=5):
     }
 
 
+def direct_flops_per_visibility(W: int) -> float:
+    """FP64 flops of the direct weights of one visibility (both axes): per axis 32 steps of the angle-sum
+    recurrence (2 multiplies + 2 FMAs) and 2 W FMAs into the taps; one sincos per axis not counted."""
+    return 2.0 * 32 * (2 + 2 * 2 + 2 * 2 * W)
+
+
+def direct_study(lmg, case, uv, vis64, reps=5):
+    """Direct calculation of the weights (lmg_table_create_direct): the workload's dirty image against the
+    direct DFT in the three modes for W = 5 and 7, the time of one dirty image + prediction (plan reused),
+    and the gridding kernel's FP64 rate (it is bound by the weights' arithmetic)."""
+    import torch
+    d = np.loadtxt(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.txt"))
+    dft = np.zeros((64, 64), dtype=np.complex128)
+    dft[d[:, 0].astype(int), d[:, 1].astype(int)] = d[:, 2] + 1j * d[:, 3]
+    pix = -1024 + 32 * np.arange(64)
+    nvis = uv.shape[0]
+    rows = []
+    for W in (5, 7):
+        table = lmg.Table.create(W, case.x0, case.table_size, case.degree).direct_calculation()
+        for name, prec in (("f32", lmg.F32), ("kahan", lmg.F32_KAHAN), ("f64", lmg.F64)):
+            plan = lmg.Plan(table, case.N, uv, prec)
+            vis = vis64.to(torch.complex128) if prec == lmg.F64 else vis64
+            img = plan.make_dirty_image(vis)
+            sel = torch.as_tensor(pix + plan.M // 2, device=img.device)
+            smp = img.index_select(0, sel).index_select(1, sel).to(torch.complex128).cpu().numpy()
+            err = float(np.linalg.norm(smp - dft) / np.linalg.norm(dft))
+            ms = _timed(lambda: plan.predict_visibilities(plan.make_dirty_image(vis)), reps)
+            lmg.trace_report()
+            lmg.trace_enable(True)
+            for _ in range(reps):
+                plan.grid(vis)
+            torch.cuda.synchronize()
+            tr = lmg.trace_report()
+            lmg.trace_enable(False)
+            n, tot = tr["grid_items"]
+            g_ms = tot / n
+            tflops = direct_flops_per_visibility(W) * nvis / (g_ms * 1e-3) / 1e12
+            rows.append({"W": W, "mode": name, "rel_rms_vs_dft": err, "ms_dirty_plus_predict": round(ms, 4),
+                         "grid_items_ms": round(g_ms, 4), "weights_fp64_tflops": round(tflops, 2),
+                         "fp64_peak_frac": round(tflops / 78.6, 3)})
+            print(f"# direct W={W} {name}: err {err:.3e}, {ms:.3f} ms, grid {g_ms:.3f} ms, {tflops:.1f} TFLOP/s",
+                  file=sys.stderr, flush=True)
+            del plan, img
+    return {"rows": rows,
+            "note": "exact kernel evaluated per visibility (no table); error = relative RMS against the FP64 "
+                    "direct DFT on the precision study's lattice; FP64 rate counts the weights' arithmetic only "
+                    "(%d flops per visibility at W = 7), peak 78.6 TFLOP/s" % direct_flops_per_visibility(7)}
+
+
 def multichannel_study(lmg, reps=5):
     """256 channels (log-uniform 1e4..2e5 visibilities), 1024^2 grids, W = 5, compensated FP32: gridding +
     degridding in one batched plan (autotuned tile) against 256 single-channel plans on one stream."""
@@ -481,6 +530,7 @@ def main():
     }
     if not args.no_studies and args.workload == "array-16m-4096":
         for key, fn in (("precision_study", lambda: precision_study(lmg, case, uv, vis.to(torch.complex64))),
+                        ("direct_weights", lambda: direct_study(lmg, case, uv, vis.to(torch.complex64))),
                         ("multichannel", lambda: multichannel_study(lmg))):
             try:
                 out[key] = fn()
