@@ -331,6 +331,36 @@ def direct_study(lmg, case, uv, vis64, reps=5):
                     "(%d flops per visibility at W = 7), peak 78.6 TFLOP/s" % direct_flops_per_visibility(7)}
 
 
+def interpolation_study(lmg, N, uv, vis, W=7, x0=0.25, sizes=(5, 9, 18, 36, 72, 144)):
+    """App. F on the device: the table's own error in an FP64 dirty image, as the relative RMS distance from
+    the direct-calculation image (same plan geometry, exact weights), for degrees 0..3 and M_s up to the
+    largest FP64 table the kernels stage in LDS. The slope of log(error) against log(M_s) over the finer
+    half should approach -(d + 1)."""
+    import torch
+    base = lmg.Table.create(W, x0, 300, 3)
+    h, _ = base.export()
+    ref_plan = lmg.Plan(base.direct_calculation(), N, uv, lmg.F64)
+    ref = ref_plan.make_dirty_image(vis)
+    nref = torch.linalg.vector_norm(ref).item()
+    del ref_plan
+    out = {}
+    for d in (0, 1, 2, 3):
+        errs = []
+        for ms in sizes:
+            plan = lmg.Plan(lmg.Table.from_h(W, x0, W * ms, d, h), N, uv, lmg.F64)
+            img = plan.make_dirty_image(vis)
+            errs.append(torch.linalg.vector_norm(img - ref).item() / nref)
+            del plan, img
+        lx, ly = np.log(np.asarray(sizes[len(sizes) // 2:], float)), np.log(np.asarray(errs[len(sizes) // 2:]))
+        slope = float(np.polyfit(lx, ly, 1)[0])
+        out[f"degree_{d}"] = {"Ms": list(sizes), "rel_rms_vs_direct": errs, "slope": round(slope, 3)}
+        print(f"# interpolation d={d}: slope {slope:.2f}, errors {['%.2e' % e for e in errs]}", file=sys.stderr,
+              flush=True)
+    out["note"] = (f"W = {W}, x0 = {x0}, FP64; error = relative RMS distance of the dirty image from the "
+                   "direct-calculation image (the table's contribution alone); slope fitted over the finer half")
+    return out
+
+
 def multichannel_study(lmg, reps=5):
     """256 channels (log-uniform 1e4..2e5 visibilities), 1024^2 grids, W = 5, compensated FP32: gridding +
     degridding in one batched plan (autotuned tile) against 256 single-channel plans on one stream."""
@@ -531,6 +561,7 @@ def main():
     if not args.no_studies and args.workload == "array-16m-4096":
         for key, fn in (("precision_study", lambda: precision_study(lmg, case, uv, vis.to(torch.complex64))),
                         ("direct_weights", lambda: direct_study(lmg, case, uv, vis.to(torch.complex64))),
+                        ("interpolation_study", lambda: interpolation_study(lmg, case.N, uv, vis.to(torch.complex128))),
                         ("multichannel", lambda: multichannel_study(lmg))):
             try:
                 out[key] = fn()
