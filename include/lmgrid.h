@@ -76,7 +76,10 @@ typedef struct lmg_table lmg_table;
 /* Optimise h by Levenberg-Marquardt (App. A; initial guess h = 1 for W <= 4,
  * h_{W-1}^2 / h_{W-2} otherwise, so W > 4 optimises the chain W = 3 .. W),
  * solve the normal equations A C = B (Eqs. 17-19) by Cholesky at every node,
- * and build the table. W in [1, 16]; x0 in (0, 0.5]; table_size >= W;
+ * and build the table. From W = 12, where A is too ill-conditioned for
+ * Cholesky (cond(A) 7e7 at W = 12), the kernel is App. B's least-squares
+ * solution by Householder QR instead, in the optimiser as well as for the
+ * nodes and the correction. W in [1, 16]; x0 in (0, 0.5]; table_size >= W;
  * degree in [0, 3]. Host only; takes milliseconds to a few seconds.
  * On success *out owns a new table (free with lmg_table_destroy). */
 lmg_status lmg_table_create(int W, double x0, int table_size, int degree, lmg_table** out);
@@ -103,7 +106,9 @@ lmg_status lmg_table_create_from_nodes(int W, double x0, int table_size, int deg
  * visibility: an arithmetic-bound variant). The grid and visibilities keep
  * the plan's precision. `from` is not modified and may be destroyed first.
  * Plans take the table like any other; the FFT, correction and crop are
- * unchanged. Errors: LMG_EINVAL (NULL argument, singular normal matrix). */
+ * unchanged. Errors: LMG_EINVAL (NULL argument, singular normal matrix);
+ * LMG_ENOTSUP for W >= 12 (the expansion multiplies by A^{-1}, whose
+ * conditioning then costs FP64 accuracy). */
 lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out);
 
 /* *direct = 1 for a table made by lmg_table_create_direct, else 0. */

@@ -121,6 +121,16 @@ def kernel_qr(h: np.ndarray, W: int, x0: float, delta, Ng: int = NG_DEFAULT) -> 
     return np.array(out).T
 
 
+QR_MIN_W = 12   # App. B: from here the normal equations lose the kernel's accuracy (cond(A) ~ 7e7 at W = 12)
+
+
+def kernel(h: np.ndarray, W: int, x0: float, delta, Ng: int = NG_DEFAULT) -> np.ndarray:
+    """The least-misfit kernel, W x n: Eq. (18) by Cholesky below W = 12, App. B's QR form from W = 12."""
+    if W >= QR_MIN_W:
+        return kernel_qr(h, W, x0, delta, Ng)
+    return kernel_from_h(h, W, x0, delta, Ng)
+
+
 # --------------------------------------------------------- misfit and LM --
 def _phase_sum(C: np.ndarray, W: int, nu: np.ndarray, x: np.ndarray) -> np.ndarray:
     """S(nu, x) = sum_r C_r(nu) exp(i 2 pi (r - nu) x), shape (n_nu, n_x)."""
@@ -139,7 +149,7 @@ def misfit_residuals(hfree: np.ndarray, W: int, x0: float, Ng: int = NG_DEFAULT,
     h = np.concatenate([[1.0], hfree])
     x, tau = coarse_x(x0, Ng)
     nu = nu_grid(Mg)
-    C = kernel_from_h(h, W, x0, nu, Ng)
+    C = kernel(h, W, x0, nu, Ng)
     r = (1.0 - h[None, :] * _phase_sum(C, W, nu, x)) * np.sqrt(tau / (x0 * Mg))[None, :]
     return np.concatenate([r.real.ravel(), r.imag.ravel()])
 
@@ -220,7 +230,7 @@ def composite_midpoint(lo: float, hi: float, n: int):
 def correction(h_coarse: np.ndarray, W: int, x0: float, N: int, Ng: int = NG_DEFAULT, nquad: int = 64) -> np.ndarray:
     """Optimal correction h(x_p) at x_p = p/N, p = -N/2 .. N/2-1 (Eq. 12 with the exact kernel)."""
     xp = (np.arange(N, dtype=np.float64) - N // 2) / N
-    _, h, _, _ = map_error(lambda d: kernel_from_h(h_coarse, W, x0, d, Ng), W, xp, nquad=nquad)
+    _, h, _, _ = map_error(lambda d: kernel(h_coarse, W, x0, d, Ng), W, xp, nquad=nquad)
     return h
 
 
@@ -238,7 +248,7 @@ def table_nodes(h_coarse: np.ndarray, W: int, x0: float, Ms: int, degree: int, N
     App. F never leave one tap's smooth branch. Shape W x (M_s + 1 + degree).
     """
     deltas = delta_low(W) + np.arange(Ms + 1 + degree, dtype=np.float64) / Ms
-    return kernel_from_h(h_coarse, W, x0, deltas, Ng)
+    return kernel(h_coarse, W, x0, deltas, Ng)
 
 
 @dataclass(frozen=True)
@@ -260,14 +270,14 @@ class ExactKernel:
     """Direct calculation of the weights (Sec. 6): the exact kernel at every offset, no table.
 
     Same interface as :class:`Table`; each call solves Eq. (18) at the given
-    offsets with :func:`kernel_from_h`.
+    offsets with :func:`kernel` (Cholesky, or QR from W = 12).
     """
     W: int
     x0: float
     h: np.ndarray
 
     def weights(self, delta) -> np.ndarray:
-        return kernel_from_h(self.h, self.W, self.x0, delta).T
+        return kernel(self.h, self.W, self.x0, delta).T
 
 
 def interpolate(nodes: np.ndarray, W: int, Ms: int, degree: int, delta) -> np.ndarray:

@@ -95,6 +95,95 @@ void gauss_legendre(int n, double a, double b, std::vector<double>& x, std::vect
     }
 }
 
+// From W = 12 the normal matrix A of Eq. 19 is too ill-conditioned (cond(A)
+// 7e7 at W = 12, 1e11 at W = 16) for the Cholesky solve to keep the kernel's
+// accuracy; App. B's least-squares form is solved by QR instead.
+constexpr int kQrMinW = 12;
+
+// App. B: C(t - delta) as the least-squares solution over the 2 N_g + 1
+// symmetric samples x_s of [-x0, x0] (trapezoid weights w_s): rows sqrt(w_s)
+// h_s (cos, sin)(2 pi (t_r - delta) x_s) against (sqrt(w_s), 0); its normal
+// equations are exactly Eq. 18. A shift of delta rotates each sample's
+// (cos, sin) row pair by the angle 2 pi delta x_s, an orthogonal map, so one
+// Householder QR of the delta = 0 matrix serves every offset:
+// C = R^{-1} Q^T g(delta), g = sqrt(w_s) (cos, sin)(2 pi delta x_s).
+struct KernelQR {
+    int W = 0, m = 0;
+    std::vector<double> a;        // m x W, column-major; Householder vectors from the diagonal down
+    std::vector<double> beta, rdiag;
+    std::vector<double> xs, sw;   // samples and square roots of their weights
+
+    bool factor(int W_, double x0, const double* h) {
+        W = W_;
+        const int ns = 2 * kNg + 1;
+        m = 2 * ns;
+        xs.resize(ns);
+        sw.resize(ns);
+        std::vector<double> hs(ns);
+        for (int s = 0; s < ns; ++s) {
+            const int i = s - kNg;                         // -N_g .. N_g
+            const int ai = i < 0 ? -i : i;
+            xs[s] = i * (x0 / kNg);
+            sw[s] = std::sqrt((ai == kNg ? 0.5 : 1.0) * (x0 / kNg));
+            hs[s] = h[ai];
+        }
+        const double ref = tap_reference(W);
+        a.assign(static_cast<size_t>(m) * W, 0.0);
+        for (int r = 0; r < W; ++r)
+            for (int s = 0; s < ns; ++s) {
+                const double ph = 2 * kPi * (r - ref) * xs[s];
+                a[static_cast<size_t>(r) * m + s] = sw[s] * hs[s] * std::cos(ph);
+                a[static_cast<size_t>(r) * m + ns + s] = sw[s] * hs[s] * std::sin(ph);
+            }
+        beta.assign(W, 0.0);
+        rdiag.assign(W, 0.0);
+        for (int k = 0; k < W; ++k) {
+            double* v = &a[static_cast<size_t>(k) * m];
+            double nrm = 0.0;
+            for (int i = k; i < m; ++i) nrm += v[i] * v[i];
+            nrm = std::sqrt(nrm);
+            if (!(nrm > 0.0)) return false;
+            const double alpha = v[k] > 0 ? -nrm : nrm;    // R_kk; v = x - alpha e_k avoids cancellation
+            v[k] -= alpha;
+            double vv = 0.0;
+            for (int i = k; i < m; ++i) vv += v[i] * v[i];
+            beta[k] = 2.0 / vv;
+            rdiag[k] = alpha;
+            for (int j = k + 1; j < W; ++j) {
+                double* col = &a[static_cast<size_t>(j) * m];
+                double sdot = 0.0;
+                for (int i = k; i < m; ++i) sdot += v[i] * col[i];
+                sdot *= beta[k];
+                for (int i = k; i < m; ++i) col[i] -= sdot * v[i];
+            }
+        }
+        return true;
+    }
+
+    // c[0..W) = C(t_j - delta).
+    void solve(double delta, double* c) const {
+        const int ns = m / 2;
+        std::vector<double> g(m);
+        for (int s = 0; s < ns; ++s) {
+            const double b = 2 * kPi * delta * xs[s];
+            g[s] = sw[s] * std::cos(b);
+            g[ns + s] = sw[s] * std::sin(b);
+        }
+        for (int k = 0; k < W; ++k) {                      // g <- Q^T g
+            const double* v = &a[static_cast<size_t>(k) * m];
+            double sdot = 0.0;
+            for (int i = k; i < m; ++i) sdot += v[i] * g[i];
+            sdot *= beta[k];
+            for (int i = k; i < m; ++i) g[i] -= sdot * v[i];
+        }
+        for (int i = W - 1; i >= 0; --i) {                 // R c = (Q^T g)[0..W)
+            double sum = g[i];
+            for (int j = i + 1; j < W; ++j) sum -= a[static_cast<size_t>(j) * m + i] * c[j];
+            c[i] = sum / rdiag[i];
+        }
+    }
+};
+
 // The optimisation problem for one (W, x0): trigonometric tables that do not
 // depend on h are built once.
 struct Problem {
@@ -148,17 +237,26 @@ struct Problem {
     // Residuals rho_{i,m} = sqrt(tau_i / (x0 M_g)) (1 - h_i S(nu_m, x_i)), (Re, Im), App. A.
     bool residuals(const double* h, double* r) const {
         std::vector<double> A;
-        normal_matrix(h, A);
-        if (!cholesky(A, W)) return false;
+        KernelQR qr;
+        if (W >= kQrMinW) {
+            if (!qr.factor(W, x0, h)) return false;
+        } else {
+            normal_matrix(h, A);
+            if (!cholesky(A, W)) return false;
+        }
         std::vector<double> c(W);
         for (int m = 0; m < kMg; ++m) {
-            for (int j = 0; j < W; ++j) {           // B_{r'}(nu) = 2 sum tau h cos(...)  (Eq. 18)
-                double s = 0.0;
-                const double* cb = &cos_b[(j * kMg + m) * (kNg + 1)];
-                for (int i = 0; i <= kNg; ++i) s += tau[i] * h[i] * cb[i];
-                c[j] = 2.0 * s;
+            if (W >= kQrMinW) {
+                qr.solve(nu[m], c.data());
+            } else {
+                for (int j = 0; j < W; ++j) {           // B_{r'}(nu) = 2 sum tau h cos(...)  (Eq. 18)
+                    double s = 0.0;
+                    const double* cb = &cos_b[(j * kMg + m) * (kNg + 1)];
+                    for (int i = 0; i <= kNg; ++i) s += tau[i] * h[i] * cb[i];
+                    c[j] = 2.0 * s;
+                }
+                cholesky_solve(A, W, c.data());
             }
-            cholesky_solve(A, W, c.data());
             for (int i = 0; i <= kNg; ++i) {
                 double sr = 0.0, si = 0.0;
                 for (int j = 0; j < W; ++j) {
@@ -248,6 +346,12 @@ bool levenberg_marquardt(const Problem& P, std::vector<double>& h, double* E_out
 
 // C(t_j - delta_k) = [A^{-1} B(delta_k)]_j for a given h (Eq. 18).
 bool exact_kernel(int W, double x0, const std::vector<double>& h, const double* delta, int n, double* out) {
+    if (W >= kQrMinW) {
+        KernelQR qr;
+        if (!qr.factor(W, x0, h.data())) return false;
+        for (int k = 0; k < n; ++k) qr.solve(delta[k], out + static_cast<size_t>(k) * W);
+        return true;
+    }
     Problem P(W, x0);
     std::vector<double> A;
     P.normal_matrix(h.data(), A);
@@ -488,6 +592,9 @@ lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out) {
     t->nodes = from->nodes;
     t->coef32 = from->coef32;
     t->coef64 = from->coef64;
+    // The expansion multiplies by A^{-1} (cond(A) eps cancellation): from W = 12 it no longer holds FP64
+    // accuracy, and the QR form of App. B has no fixed expansion of this kind.
+    if (t->W >= kQrMinW) return LMG_ENOTSUP;
     t->direct = true;
     if (!direct_coefficients(t->W, t->x0, t->h, t->pq)) return LMG_EINVAL;
     *out = t.release();

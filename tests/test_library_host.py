@@ -44,6 +44,29 @@ def test_table_optimiser_matches_oracle_at_optimiser_level(W):
     assert np.max(np.abs(h_lib / h_or - 1)) < 1e-4
 
 
+@pytest.mark.parametrize("W", [12, 14])
+def test_wide_tables_by_qr(W):
+    """From W = 12 both sides solve App. B's least squares by QR (the library through one factorisation and
+    rotated right-hand sides, the oracle by a least-squares solve per offset): the same h gives the same
+    kernel and correction, and the library's optimiser reaches the oracle's misfit level."""
+    t = lmg.Table.create(W, 0.25, 300, 3)
+    h_lib, _ = t.export()
+    E_or = lt.integrated_misfit_coarse(h_lib, W, 0.25)
+    # the same E formula on the same h; E sums squares of residuals rho ~ sqrt(E / 1056) made of O(1) terms,
+    # so rounding of ~4 eps in each rho moves E by ~8 eps / rho relative (about 1 % at W = 14)
+    rho = np.sqrt(E_or / 1056)
+    assert abs(t.integrated_misfit - E_or) <= max(1e-3, 4 * 8 * 2.2e-16 / rho) * E_or
+    assert t.integrated_misfit < (5e-24 if W == 12 else 5e-28)      # below the Cholesky-limited optimum
+    d = np.linspace(-0.5, 0.5, 13) if W % 2 else np.linspace(0.0, 1.0, 13)
+    np.testing.assert_allclose(t.kernel(d).T, lt.kernel(h_lib, W, 0.25, d), rtol=0, atol=1e-11)
+    _, nodes = t.export()
+    np.testing.assert_allclose(nodes, lt.table_nodes(h_lib, W, 0.25, 300 // W, 3), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(t.correction(256), lt.correction(h_lib, W, 0.25, 256), rtol=1e-10)
+    lib = lmg.load()
+    out = ctypes.c_void_p()
+    assert lib.lmg_table_create_direct(t.handle, ctypes.byref(out)) == -5       # LMG_ENOTSUP
+
+
 def test_table_from_h_matches_oracle_nodes():
     h = lt.optimal_h(7, 0.25)
     t = lmg.Table.from_h(7, 0.25, 300, 3, h)

@@ -115,6 +115,19 @@ def test_correction_fixed_point(W):
     np.testing.assert_allclose(h, c / D, rtol=5e-9)
 
 
+def test_qr_optimum_keeps_falling_past_w11():
+    """App. B: with the kernel solved by QR from W = 12, the optimised misfit keeps falling with W (Sec. 2.2),
+    to sqrt(E) ~ 1e-14 at W = 14, FP64's limit; the normal-equation solve departs from QR there by
+    cond(A) eps (5e-10 at W = 12), enough to stall the optimiser."""
+    E = {W: lt.integrated_misfit_coarse(lt.optimal_h(W, 0.25), W, 0.25) for W in (11, 12, 13, 14)}
+    assert E[11] > 10 * E[12] > 100 * E[13] > 1000 * E[14]
+    assert np.sqrt(E[14]) < 1e-13
+    h = lt.optimal_h(12, 0.25)
+    d = np.linspace(-0.5, 0.5, 9)
+    diff = np.max(np.abs(lt.kernel_from_h(h, 12, 0.25, d) - lt.kernel(h, 12, 0.25, d)))
+    assert 1e-12 < diff < 1e-15 * np.linalg.cond(lt.normal_matrix(h, 12, 0.25)) * 100
+
+
 @pytest.mark.parametrize("W", [2, 3, 5, 7, 9])
 def test_correction_shape(W):
     """h(0) = 1 and h increases on [0, x0] for W >= 2 (App. A; Sec. 3)."""
