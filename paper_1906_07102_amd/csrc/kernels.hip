@@ -4,20 +4,23 @@
 // over the W cells S_k (Sec. 2.1, Eqs. 5-6), the FFT dirty image with
 // correction h(x) and cropping to |x| <= x0 (Eq. 4), and degridding as the
 // transpose (Sec. 1, Sec. 5). The tabulated kernel is read with nearest-node
-// or Newton forward interpolation (App. E-F).
+// or Newton forward interpolation (App. E-F), or, for a direct table,
+// evaluated exactly per visibility (Eq. 18; Sec. 6's direct calculation).
 //
 // Work decomposition. The plan (built once per uv set) counting-sorts the
 // visibilities by uv tile of T x T cells and splits dense tiles into work
 // items of at most `cap` visibilities. Inside an item the visibilities are
-// ordered by footprint cell (the first tap cell, which fixes all W x W taps)
-// and cut into "pieces": at most kPiece visibilities of one cell. A lane
-// takes one piece, keeps the W x W sums (gridding) or the W x W grid values
-// (degridding) of that cell in registers for the whole piece, and touches
-// LDS once per piece; all lanes of a wave do so together. Each item
-// accumulates a (T + W - 1)^2 patch in LDS and writes it out; the assemble
-// kernel adds the patches of each tile and of the three neighbours whose
-// halos overlap it, in a fixed order, writing every grid cell exactly once.
-// Visibility data are permuted once per call into this entry order.
+// grouped by footprint cell (the first tap cell, which fixes all W x W taps)
+// and cut into "pieces": at most kPiece visibilities of one cell, laid out
+// in the order the gridding kernel takes them (full pieces cell by cell,
+// then the tails, longest first). In gridding a lane takes one piece, keeps
+// the W x W sums of that cell in registers for the whole piece and touches
+// LDS once per piece; each item accumulates a (T + W - 1)^2 patch in LDS and
+// writes it out, and the assemble kernel adds the patches of each tile and
+// of the three neighbours whose halos overlap it, in a fixed order, writing
+// every grid cell exactly once. In degridding the item's patch of the grid
+// is staged in LDS and a lane takes one visibility. Visibility data are
+// permuted once per call into this entry order.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
