@@ -53,6 +53,7 @@ struct GridArgs {
 struct AssembleArgs {
     int N, W, T, ntx, nchan;
     int tr0, tc0, trows, tcols;   // window of tiles written (rows tr0.., columns tc0.., wrapping)
+    int rows;                     // tile rows per workgroup (set by the launcher)
     const int* item_start;   // per tile, ntiles + 1
     const void* patches;
     void* grid;

@@ -982,18 +982,18 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
 
 // Sum the patches covering each tile (own tile, left, upper, upper-left
 // neighbours, in that fixed order) and write every grid cell once. One
-// workgroup per kAssembleRows rows of a tile.
-constexpr int kAssembleRows = 8;
+// workgroup per a.rows rows of a tile (chosen by the launcher).
 
 template <typename R, typename Acc>
 __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
     using VT = typename C2<R>::T;
     using Cell = typename Acc::Cell;
-    const int nblk = a.T / kAssembleRows;
+    const int ar = a.rows;
+    const int nblk = a.T / ar;
     const int per_chan = a.trows * a.tcols;
     const int chan = blockIdx.x / (nblk * per_chan);
     const int wt = (blockIdx.x / nblk) % per_chan;          // tile within the written window
-    const int rb = (blockIdx.x % nblk) * kAssembleRows;
+    const int rb = (blockIdx.x % nblk) * ar;
     const int tm = (a.tr0 + wt / a.tcols) % a.ntx, tn = (a.tc0 + wt % a.tcols) % a.ntx;
     const int ntiles = a.ntx * a.ntx;
     const int cbase = chan * ntiles;                        // global tiles of this channel
@@ -1014,7 +1014,7 @@ __global__ __launch_bounds__(256) void k_assemble(AssembleArgs a) {
         i0[s] = a.item_start[src_t[s]];
         i1[s] = a.item_start[src_t[s] + 1];
     }
-    for (int cell = threadIdx.x; cell < kAssembleRows * a.T; cell += blockDim.x) {
+    for (int cell = threadIdx.x; cell < ar * a.T; cell += blockDim.x) {
         const int lr = rb + cell / a.T, lc = cell % a.T;
         double sr = 0.0, si = 0.0;      // the few partial sums per cell are merged in FP64
         for (int s = 0; s < 4; ++s) {
@@ -1504,9 +1504,14 @@ hipError_t launch_zero_ints(int* p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_t s) {
-    const unsigned nt = static_cast<unsigned>(static_cast<int64_t>(a.nchan) * a.trows * a.tcols *
-                                              (a.T / dev::kAssembleRows));
+hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& args, hipStream_t s) {
+    // Rows of a tile per workgroup: 8 while the window has few tiles (the dense ones split over several
+    // workgroups, for balance); about 1,024 cells when it has many, as in a batched plan's full grids of
+    // mostly empty tiles, where smaller workgroups make the write bound by workgroup dispatch.
+    AssembleArgs a = args;
+    const int64_t tiles = static_cast<int64_t>(a.nchan) * a.trows * a.tcols;
+    a.rows = tiles > 32768 ? std::min(a.T, 1024 / a.T) : std::min(a.T, 8);
+    const unsigned nt = static_cast<unsigned>(tiles * (a.T / a.rows));
     if (nt == 0) return hipSuccess;
     switch (prec) {
         case LMG_F32: hipLaunchKernelGGL((dev::k_assemble<float, dev::AccF32>), dim3(nt), dim3(256), 0, s, a); break;
