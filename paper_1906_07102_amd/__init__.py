@@ -440,7 +440,8 @@ def autotune_batch(table: Table, N: int, uv, offsets, vis, weights=None, precisi
                    tiles=(16, 32, 64), reps: int = 3, stream=None):
     """Pick the uv tile edge of a batched plan by timing gridding + degridding on the caller's data.
 
-    Each candidate tile (skipped where the library rejects it) gets a plan, one
+    Each candidate tile (skipped where the library rejects it as invalid or
+    unsupported; any other failure propagates) gets a plan, one
     untimed grid + degrid, then ``reps`` timed ones (HIP events on the launch
     stream). The fastest plan is returned with the timings {tile: ms}; the
     choice is remembered for the same (N, W, precision, channels, visibilities).
@@ -457,7 +458,9 @@ def autotune_batch(table: Table, N: int, uv, offsets, vis, weights=None, precisi
             continue
         try:
             plan = BatchPlan(table, N, uv, off, precision, T, stream)
-        except LmgError:
+        except LmgError as e:
+            if e.status not in (-1, -5):            # only LMG_EINVAL / LMG_ENOTSUP mean "tile not usable"
+                raise
             continue
         g = plan.grid(vis, weights, stream=s)
         v = plan.degrid(g, stream=s)
