@@ -82,6 +82,7 @@ TRACE_TO_SYMBOL = {
     "plan_compose": "k_plan_compose",
     "permute_in": "k_permute_in", "grid_items": "k_grid_items", "assemble": "k_assemble",
     "degrid_items": "k_degrid_items", "permute_out": "k_permute_out",
+    "fft_pass": "k_fft_pass",            # the four passes of a step (summaries take the median)
 }
 CALIBRATION_SYMBOL = "MulFunctor"       # torch.mul(a, 1.0, out=b) over 2^28 floats: 1 GiB read + 1 GiB written
 CALIBRATION_BYTES = float(1 << 30)
@@ -197,6 +198,39 @@ def summarize_read_sizes(csv_path: str, command: str, nvis: int) -> str:
         tot = max(a[i], 1.0)
         lines.append(f"{trace:24s} {names[0][:44]:44s} {by[i] / 1e6:9.2f} {by[i] / nvis:7.2f} "
                      f"{b[i] / tot:6.2f} {c[i] / tot:6.2f} {d[i] / tot:6.2f}")
+    return "\n".join(lines) + "\n"
+
+
+def summarize_counters(csv_paths, command: str) -> str:
+    """Per-kernel medians (over dispatches) of every counter in one or more --pmc counter_collection.csv files,
+    with each SQ wave-cycle counter also given as a fraction of SQ_WAVE_CYCLES."""
+    import csv
+    counters = []
+    for path in csv_paths:
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] not in counters:
+                counters.append(r["Counter_Name"])
+    per = {}
+    for path in csv_paths:
+        for c in counters:
+            for k, vs in _counter_per_dispatch(path, c).items():
+                if vs:
+                    per.setdefault(k, {})[c] = float(np.median(vs))
+    cyc = "SQ_WAVE_CYCLES"
+    lines = ["# hardware counters per launch (median over dispatches)", f"# command: {command}", ""]
+    for trace, sym in TRACE_TO_SYMBOL.items():
+        names = [k for k in per if k.startswith(sym + "<") or k == sym]
+        if not names:
+            continue
+        d = per[names[0]]
+        lines.append(f"{trace} ({names[0]})")
+        for c in counters:
+            if c not in d:
+                continue
+            frac = ""
+            if cyc in d and c != cyc and d[cyc] > 0 and ("WAIT" in c or "ACTIVE" in c or "BUSY" in c):
+                frac = f"   ({d[c] / d[cyc]:.3f} of {cyc})"
+            lines.append(f"  {c:28s} {d[c]:16.0f}{frac}")
     return "\n".join(lines) + "\n"
 
 
@@ -418,11 +452,16 @@ def main():
                     help="write profiles/traffic.json from FETCH_SIZE and WRITE_SIZE passes, print a summary, exit")
     ap.add_argument("--summarize-read-sizes", metavar="COUNTER_CSV",
                     help="print read bytes per launch from a pass with the sized read-request counters, exit")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="COUNTER_CSV",
+                    help="print per-kernel medians of the counters of one or more --pmc passes, exit")
     ap.add_argument("--profile-command", default="", help="command line recorded in a summary")
     ap.add_argument("--nvis", type=int, default=16777152, help="visibilities of the profiled run (traffic summary)")
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.profile_command), end="")
+        return
+    if args.summarize_counters:
+        print(summarize_counters(args.summarize_counters, args.profile_command), end="")
         return
     if args.summarize_read_sizes:
         print(summarize_read_sizes(args.summarize_read_sizes, args.profile_command, args.nvis), end="")
