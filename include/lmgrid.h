@@ -185,10 +185,18 @@ lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes);
 
 /* --------------------------------------------------------- planned calls */
 
-/* Gridding (Eq. 5 in 2D): grid[m][n] = sum_k w_k V_k C(m - v_k) C(n - u_k),
- * OVERWRITING the N x N device grid. vis: device complex (nvis), w: device
- * float32 (nvis) or NULL for unit weights. */
-lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid,
+/* Gridding (Eq. 5 in 2D): G[m][n] = sum_k w_k V_k C(m - v_k) C(n - u_k) over
+ * the plan's visibilities. accumulate = 0 overwrites the N x N device grid
+ * (every cell is written, zero where no footprint reaches); accumulate = 1
+ * adds G to what the grid holds (grid += G), reading and writing only the uv
+ * tiles that receive contributions, so that chunks of a visibility set (or
+ * channels) can be summed into one grid: Eq. 5 is a sum over k. Any other
+ * value: LMG_EINVAL. vis: device complex (nvis), w: device float32 (nvis) or
+ * NULL for unit weights. The sum is computed in the plan's precision (FP32,
+ * compensated FP32 with (hi, lo) pairs, or FP64) in an order fixed by the
+ * plan, so repeated calls on the same plan and data give identical bits, and
+ * so do plans built again from the same coordinates. */
+lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, int accumulate,
                             void* scratch, size_t scratch_bytes, void* stream);
 
 /* Degridding, the transpose of gridding (Sec. 1, Sec. 5):
@@ -199,7 +207,10 @@ lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out
 
 /* Dirty image (Eq. 4 in 2D): grid, inverse 2D FFT (exponent +i2pi), multiply
  * by h(x_p) h(y_q) and keep |x|, |y| <= x0. image: device complex
- * (2 x0 N)^2, overwritten. No normalisation by sum(w). */
+ * (2 x0 N)^2, overwritten. No normalisation by sum(w). The transforms are
+ * pruned to the occupied band of the grid, which the plan's counts give: the
+ * first image or prediction call on a plan waits on the host for the plan's
+ * kernels (after its gridding kernels are queued); later calls do not. */
 lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image,
                                         void* scratch, size_t scratch_bytes, void* stream);
 
@@ -213,7 +224,10 @@ lmg_status lmg_predict_visibilities_planned(const lmg_plan* p, const void* image
  * Build a plan inside `workspace`, run the call, and release the plan. The
  * workspace size comes from lmg_workspace_size for the same (N, W, nvis,
  * prec, op). They return after the plan's kernels have finished (the plan is
- * released), so they may block the host. */
+ * released), so they may block the host. lmg_grid ACCUMULATES: grid += G
+ * (the caller zeroes the grid first), so that a visibility set too large for
+ * one call (nvis <= INT32_MAX per plan) is streamed into one grid in chunks.
+ * The other three overwrite their outputs. */
 lmg_status lmg_workspace_size(int N, int W, double x0, int64_t nvis, lmg_precision prec, int op, size_t* bytes);
 lmg_status lmg_grid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv,
                     const void* vis, const float* w, void* grid, void* workspace, size_t ws_bytes, void* stream);
@@ -237,9 +251,10 @@ lmg_status lmg_predict_visibilities(const lmg_table* t, int N, lmg_precision pre
  * and then read / write nchan grids; lmg_make_dirty_image_planned and
  * lmg_predict_visibilities_planned return LMG_ENOTSUP for nchan > 1.
  * tile: edge of the uv tiles in cells, 0 for the library default, else a
- * power of two in [8, min(128, N)] with N / tile <= 128 (LMG_EINVAL
- * otherwise); the best value depends on the density of the data, which is
- * what an autotuner measures. Workspace sizes are upper bounds for any tile.
+ * power of two in [max(8, W), min(128, N)] with N / tile <= 128 (LMG_EINVAL
+ * otherwise: a footprint of W cells must not reach two tiles away); the best
+ * value depends on the density of the data, which is what an autotuner
+ * measures. Workspace sizes are upper bounds for any tile.
  */
 lmg_status lmg_batch_workspace_size(int N, int W, int nchan, int64_t nvis, lmg_precision prec, size_t* bytes);
 lmg_status lmg_batch_plan_create(const lmg_table* table, int N, lmg_precision prec, int nchan, const int64_t* offsets,
@@ -248,7 +263,7 @@ lmg_status lmg_batch_plan_create(const lmg_table* table, int N, lmg_precision pr
 /* Channels, tile edge and waves per gridding workgroup of a plan (any pointer may be NULL). */
 lmg_status lmg_batch_info(const lmg_plan* p, int* nchan, int* tile, int* waves);
 
-/* One-shot batched gridding (overwrites all nchan grids) and degridding; op is
+/* One-shot batched gridding (accumulates into all nchan grids: grids += G_c) and degridding; op is
  * LMG_OP_GRID or LMG_OP_DEGRID. They return after the plan's kernels have
  * finished (the plan is released), so they may block the host. */
 lmg_status lmg_workspace_size_batched(int N, int W, int nchan, int64_t nvis, lmg_precision prec, int op,
@@ -278,6 +293,14 @@ lmg_status lmg_trace_report(char* buf, size_t len);
 /* Record only the kernel of this trace name ("grid_items", "plan_scatter",
  * ...); NULL or "" records every kernel again. The name is copied. */
 lmg_status lmg_trace_only(const char* name);
+
+/* Wait for all work enqueued on `stream` (a hipStream_t as void*, NULL = the
+ * null stream), then report device-side data errors: LMG_EDATA if any plan
+ * built on the current device since the last call met non-finite uv
+ * coordinates (those visibilities were dropped), else LMG_OK; LMG_EHIP if a
+ * HIP call failed. The device-wide flag is cleared by the call that reports
+ * it. Host-blocking. */
+lmg_status lmg_sync_status(void* stream);
 
 const char* lmg_status_string(lmg_status s);
 

@@ -20,7 +20,7 @@ import numpy as np
 __all__ = [
     "F32", "F32_KAHAN", "F64", "LmgError", "LibraryMissing", "Table", "Plan", "BatchPlan", "autotune_batch",
     "library_path", "load", "grid", "degrid", "make_dirty_image", "predict_visibilities", "grid_batched",
-    "degrid_batched", "fft2_centred", "trace_enable", "trace_only", "trace_report", "Degrid", "Grid", "PredictVisibilities",
+    "degrid_batched", "fft2_centred", "sync_status", "trace_enable", "trace_only", "trace_report", "Degrid", "Grid", "PredictVisibilities",
     "MakeDirtyImage",
 ]
 
@@ -87,7 +87,7 @@ def load():
         "lmg_plan_info": (I, [P, PI, PI, PI, ctypes.POINTER(I64)]),
         "lmg_plan_destroy": (None, [P]),
         "lmg_plan_scratch_size": (I, [P, I, PZ]),
-        "lmg_grid_planned": (I, [P, P, P, P, P, Z, P]),
+        "lmg_grid_planned": (I, [P, P, P, P, I, P, Z, P]),
         "lmg_degrid_planned": (I, [P, P, P, P, Z, P]),
         "lmg_make_dirty_image_planned": (I, [P, P, P, P, P, Z, P]),
         "lmg_predict_visibilities_planned": (I, [P, P, P, P, Z, P]),
@@ -106,6 +106,7 @@ def load():
         "lmg_trace_enable": (I, [I]),
         "lmg_trace_report": (I, [ctypes.c_char_p, Z]),
         "lmg_trace_only": (I, [ctypes.c_char_p]),
+        "lmg_sync_status": (I, [P]),
         "lmg_status_string": (ctypes.c_char_p, [I]),
         "lmg_last_error": (ctypes.c_char_p, []),
     }
@@ -249,18 +250,57 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _check_tensor(t, name, dtype=None, shape=None, device=None):
+def _check_tensor(t, name, dtype=None, shape=None, device=None, on_device=True):
+    """Type, dtype, shape and layout first, then (unless on_device is False) that the tensor is on the device."""
     torch = _torch()
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if not t.is_contiguous():
-        raise ValueError(f"{name} must be contiguous")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not on_device:
+        return
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if device is not None and t.device != device:
         raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _check_uv(uv):
+    """uv: float64 (nvis, 2), contiguous, on a device; returns nvis."""
+    torch = _torch()
+    if not isinstance(uv, torch.Tensor):
+        raise TypeError("uv must be a torch tensor")
+    if uv.dim() != 2 or uv.shape[1] != 2:
+        raise ValueError(f"uv must be (nvis, 2), got {tuple(uv.shape)}")
+    _check_tensor(uv, "uv", torch.float64, on_device=False)
+    return int(uv.shape[0])
+
+
+def _check_vis_weights(vis, weights, nvis):
+    torch = _torch()
+    if not isinstance(vis, torch.Tensor) or vis.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("visibilities must be a complex64 or complex128 tensor")
+    _check_tensor(vis, "vis", vis.dtype, (nvis,), on_device=False)
+    if weights is not None:
+        _check_tensor(weights, "weights", torch.float32, (nvis,), on_device=False)
+
+
+def _on_one_device(**tensors):
+    """Every given tensor (None skipped) is a device tensor, all on the same device."""
+    dev = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, expected {dev}")
 
 
 def _bytes(n: int, device):
@@ -322,17 +362,20 @@ class Plan:
     def _vis_dtype(self):
         return _cdtype(self.precision)
 
-    def grid(self, vis, weights=None, out=None, stream=None):
+    def grid(self, vis, weights=None, out=None, accumulate: bool = False, stream=None):
+        """Gridding (lmg_grid_planned): a new grid, ``out`` overwritten, or ``out += G`` with ``accumulate``."""
         torch = _torch()
         _check_tensor(vis, "vis", self._vis_dtype(), (self.nvis,), self.device)
         if weights is not None:
             _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
         if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs an output grid")
             out = torch.empty(self.grid_shape, dtype=self._vis_dtype(), device=self.device)
         _check_tensor(out, "grid", self._vis_dtype(), self.grid_shape, self.device)
         sc = self.scratch(OP_GRID)
-        _check(self.lib.lmg_grid_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), _ptr(sc), sc.numel(),
-                                         _stream_handle(stream)), "lmg_grid_planned")
+        _check(self.lib.lmg_grid_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), 1 if accumulate else 0,
+                                         _ptr(sc), sc.numel(), _stream_handle(stream)), "lmg_grid_planned")
         return out
 
     def degrid(self, grid, out=None, stream=None):
@@ -481,18 +524,32 @@ def autotune_batch(table: Table, N: int, uv, offsets, vis, weights=None, precisi
     return best[1], timings
 
 
-def grid_batched(table: Table, N: int, uv, offsets, vis, weights=None, kahan: bool = False, stream=None):
-    """One-shot batched gridding (plan built and released inside); returns (nchan, N, N) grids."""
+def _check_offsets(off, nvis):
+    if off[0] != 0 or np.any(np.diff(off) < 0) or off[-1] != nvis:
+        raise ValueError(f"offsets must start at 0, not decrease and end at nvis = {nvis}")
+
+
+def grid_batched(table: Table, N: int, uv, offsets, vis, weights=None, kahan: bool = False, out=None,
+                 stream=None):
+    """One-shot batched gridding (plan built and released inside). lmg_grid_batched accumulates: into ``out``
+    (nchan, N, N) if given, else into new zeroed grids, which are returned."""
     torch = _torch()
+    nvis = _check_uv(uv)
+    _check_vis_weights(vis, weights, nvis)
     prec = _prec_of(vis.dtype, kahan)
     off = _offsets_array(offsets)
+    _check_offsets(off, nvis)
     nchan = len(off) - 1
+    if out is not None:
+        _check_tensor(out, "grids", vis.dtype, (nchan, N, N), on_device=False)
+    _on_one_device(uv=uv, vis=vis, weights=weights, grids=out)
     lib = load()
     nb = ctypes.c_size_t()
     _check(lib.lmg_workspace_size_batched(int(N), table.W, nchan, int(off[-1]), prec, OP_GRID, ctypes.byref(nb)),
            "lmg_workspace_size_batched")
     ws = _bytes(nb.value, vis.device)
-    out = torch.empty((nchan, N, N), dtype=vis.dtype, device=vis.device)
+    if out is None:
+        out = torch.zeros((nchan, N, N), dtype=vis.dtype, device=vis.device)
     _check(lib.lmg_grid_batched(table.handle, int(N), prec, nchan, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                 _ptr(uv), _ptr(vis), _ptr(weights), _ptr(out), _ptr(ws), nb.value,
                                 _stream_handle(stream)), "lmg_grid_batched")
@@ -502,9 +559,15 @@ def grid_batched(table: Table, N: int, uv, offsets, vis, weights=None, kahan: bo
 def degrid_batched(table: Table, N: int, uv, offsets, grids, stream=None):
     """One-shot batched degridding of (nchan, N, N) grids."""
     torch = _torch()
-    prec = _prec_of(grids.dtype, False)
+    nvis = _check_uv(uv)
+    if not isinstance(grids, torch.Tensor) or grids.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("grids must be a complex64 or complex128 tensor")
     off = _offsets_array(offsets)
+    _check_offsets(off, nvis)
     nchan = len(off) - 1
+    _check_tensor(grids, "grids", grids.dtype, (nchan, N, N), on_device=False)
+    _on_one_device(uv=uv, grids=grids)
+    prec = _prec_of(grids.dtype, False)
     lib = load()
     nb = ctypes.c_size_t()
     _check(lib.lmg_workspace_size_batched(int(N), table.W, nchan, int(off[-1]), prec, OP_DEGRID, ctypes.byref(nb)),
@@ -637,22 +700,33 @@ def _oneshot_ws(table, N, nvis, prec, op, device):
     return _bytes(n.value, device), n.value
 
 
-def grid(table: Table, N: int, uv, vis, weights=None, kahan: bool = False, stream=None):
-    """One-shot gridding (builds a plan internally); returns the N x N grid."""
+def grid(table: Table, N: int, uv, vis, weights=None, kahan: bool = False, out=None, stream=None):
+    """One-shot gridding (builds a plan internally). lmg_grid accumulates: into ``out`` if given, else into a
+    new zeroed N x N grid, which is returned."""
     torch = _torch()
+    nvis = _check_uv(uv)
+    _check_vis_weights(vis, weights, nvis)
     prec = _prec_of(vis.dtype, kahan)
-    _check_tensor(uv, "uv", torch.float64)
-    out = torch.empty((N, N), dtype=vis.dtype, device=vis.device)
-    ws, nb = _oneshot_ws(table, N, vis.numel(), prec, OP_GRID, vis.device)
-    _check(load().lmg_grid(table.handle, N, prec, vis.numel(), _ptr(uv), _ptr(vis), _ptr(weights), _ptr(out),
+    if out is not None:
+        _check_tensor(out, "grid", vis.dtype, (N, N), on_device=False)
+    _on_one_device(uv=uv, vis=vis, weights=weights, grid=out)
+    if out is None:
+        out = torch.zeros((N, N), dtype=vis.dtype, device=vis.device)
+    ws, nb = _oneshot_ws(table, N, nvis, prec, OP_GRID, vis.device)
+    _check(load().lmg_grid(table.handle, N, prec, nvis, _ptr(uv), _ptr(vis), _ptr(weights), _ptr(out),
                            _ptr(ws), nb, _stream_handle(stream)), "lmg_grid")
     return out
 
 
 def degrid(table: Table, N: int, uv, grid_, stream=None):
+    """One-shot degridding of an N x N grid at the uv coordinates."""
     torch = _torch()
+    nvis = _check_uv(uv)
+    if not isinstance(grid_, torch.Tensor) or grid_.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("grid must be a complex64 or complex128 tensor")
+    _check_tensor(grid_, "grid", grid_.dtype, (N, N), on_device=False)
+    _on_one_device(uv=uv, grid=grid_)
     prec = _prec_of(grid_.dtype, False)
-    nvis = uv.shape[0]
     out = torch.empty(nvis, dtype=grid_.dtype, device=grid_.device)
     ws, nb = _oneshot_ws(table, N, nvis, prec, OP_DEGRID, grid_.device)
     _check(load().lmg_degrid(table.handle, N, prec, nvis, _ptr(uv), _ptr(grid_), _ptr(out), _ptr(ws), nb,
@@ -661,25 +735,44 @@ def degrid(table: Table, N: int, uv, grid_, stream=None):
 
 
 def make_dirty_image(table: Table, N: int, uv, vis, weights=None, kahan: bool = False, stream=None):
+    """One-shot dirty image (grid, inverse FFT, correct, crop)."""
     torch = _torch()
+    nvis = _check_uv(uv)
+    _check_vis_weights(vis, weights, nvis)
+    _on_one_device(uv=uv, vis=vis, weights=weights)
     prec = _prec_of(vis.dtype, kahan)
     M = int(round(2 * table.x0 * N))
     out = torch.empty((M, M), dtype=vis.dtype, device=vis.device)
-    ws, nb = _oneshot_ws(table, N, vis.numel(), prec, OP_DIRTY, vis.device)
-    _check(load().lmg_make_dirty_image(table.handle, N, prec, vis.numel(), _ptr(uv), _ptr(vis), _ptr(weights),
+    ws, nb = _oneshot_ws(table, N, nvis, prec, OP_DIRTY, vis.device)
+    _check(load().lmg_make_dirty_image(table.handle, N, prec, nvis, _ptr(uv), _ptr(vis), _ptr(weights),
                                        _ptr(out), _ptr(ws), nb, _stream_handle(stream)), "lmg_make_dirty_image")
     return out
 
 
 def predict_visibilities(table: Table, N: int, uv, image, stream=None):
+    """One-shot prediction (correct, pad, forward FFT, degrid) of an M x M image, M = 2 x0 N."""
     torch = _torch()
+    nvis = _check_uv(uv)
+    M = int(round(2 * table.x0 * N))
+    if not isinstance(image, torch.Tensor) or image.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("image must be a complex64 or complex128 tensor")
+    _check_tensor(image, "image", image.dtype, (M, M), on_device=False)
+    _on_one_device(uv=uv, image=image)
     prec = _prec_of(image.dtype, False)
-    nvis = uv.shape[0]
     out = torch.empty(nvis, dtype=image.dtype, device=image.device)
     ws, nb = _oneshot_ws(table, N, nvis, prec, OP_PREDICT, image.device)
     _check(load().lmg_predict_visibilities(table.handle, N, prec, nvis, _ptr(uv), _ptr(image), _ptr(out), _ptr(ws),
                                            nb, _stream_handle(stream)), "lmg_predict_visibilities")
     return out
+
+
+def sync_status(stream=None) -> int:
+    """lmg_sync_status: wait for the stream, then 0 (LMG_OK) or -4 (LMG_EDATA: non-finite coordinates were met
+    by a plan on this device since the last call; the flag is cleared)."""
+    s = load().lmg_sync_status(_stream_handle(stream))
+    if s not in (0, -4):
+        raise LmgError(s, "lmg_sync_status")
+    return s
 
 
 def trace_enable(on: bool = True):
@@ -705,7 +798,13 @@ def trace_report() -> dict:
 
 def fft2_centred(data, sign: int, stream=None):
     """In-place centred 2D FFT of an N x N complex tensor (exponent sign * i 2 pi)."""
-    N = data.shape[0]
+    torch = _torch()
+    if not isinstance(data, torch.Tensor) or data.dim() != 2 or data.shape[0] != data.shape[1]:
+        raise ValueError("data must be an N x N tensor")
+    N = int(data.shape[0])
+    if data.dtype not in (torch.complex64, torch.complex128):
+        raise TypeError("data must be complex64 or complex128")
+    _check_tensor(data, "data", data.dtype, (N, N))
     prec = _prec_of(data.dtype, False)
     cs = 16 if prec == F64 else 8
     scratch = _bytes(((N * N * cs + 255) // 256) * 256 + N * cs, data.device)

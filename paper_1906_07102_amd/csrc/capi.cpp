@@ -94,10 +94,20 @@ int env_int(const char* name, int fallback) {
     return x > 0 ? x : fallback;
 }
 
-int choose_tile(int N, lmg_precision prec) {
+// Smallest tile edge the plan accepts for support W: a power of two >= W,
+// and at least 8. The assemble kernel adds a tile's patch to its right and
+// lower neighbours only, so a footprint (W cells) must not reach two tiles
+// away (Eq. 6: S_k has W cells).
+int min_tile(int W) {
+    int T = 8;
+    while (T < W) T *= 2;
+    return T;
+}
+
+int choose_tile(int N, int W) {
     int T = env_int("LMG_TILE", 32);
-    (void)prec;
     if (!is_pow2(T) || T < 8) T = 32;
+    T = std::max(T, min_tile(W));
     T = std::min(T, 128);
     while (T > N) T /= 2;
     while (N / T > 128) T *= 2;    // keeps the plan's LDS histogram at <= 16384 tiles
@@ -108,7 +118,8 @@ int choose_tile(int N, lmg_precision prec) {
 // workgroup's LDS; where the tile cannot shrink (at most 128 x 128 tiles),
 // fewer waves per workgroup (fit_waves).
 int fit_tile(int T, int N, lmg_precision prec, int W, int Ms) {
-    while (T > 8 && grid_lds_bytes(prec, W, T, Ms, kMaxGridWaves) > kMaxDynLds && N / (T / 2) <= 128) T /= 2;
+    while (T / 2 >= min_tile(W) && grid_lds_bytes(prec, W, T, Ms, kMaxGridWaves) > kMaxDynLds && N / (T / 2) <= 128)
+        T /= 2;
     return T;
 }
 // Waves (private patches) per gridding workgroup: the count that lets a
@@ -432,8 +443,11 @@ lmg_status wait_plan(const lmg_plan* p, hipStream_t s) {
     return LMG_OK;
 }
 
+// Gridding through the plan: overwrite the grid (every cell of the window
+// written), or add to it (accumulate: only tiles that receive patches are
+// read and written).
 lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
-                    int* counters, hipStream_t s, bool band_only = false) {
+                    int* counters, hipStream_t s, bool band_only, bool accumulate) {
     const lmg_table* t = p->table;
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters, kCounters, s));
@@ -452,6 +466,7 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     }
     AssembleArgs b{};
     b.N = p->g.N; b.W = p->g.W; b.T = p->g.T; b.ntx = p->g.ntx; b.nchan = p->nchan;
+    b.accumulate = accumulate ? 1 : 0;
     if (band_only) {                  // an internal grid: only the occupied window is ever read
         const lmg_status st = ensure_flags(p);     // the grid kernels are already queued
         if (st != LMG_OK) return st;
@@ -518,10 +533,12 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
         if (offsets[c + 1] < offsets[c]) return LMG_EINVAL;
     const int64_t nvis = offsets[nchan];
     if (nvis < 0 || nvis > INT32_MAX || (nvis > 0 && !uv)) return LMG_EINVAL;
-    if (tile != 0 && (!is_pow2(tile) || tile < 8 || tile > 128 || tile > N || N / tile > 128)) return LMG_EINVAL;
+    if (tile != 0 && (!is_pow2(tile) || tile < 8 || tile < table->W || tile > 128 || tile > N || N / tile > 128))
+        return LMG_EINVAL;
     const size_t tab_bytes = coef_bytes(table, prec);
     if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
-    const int T = tile ? tile : fit_tile(choose_tile(N, prec), N, prec, table->W, staged_ms(table));
+    const int T = tile ? tile : fit_tile(choose_tile(N, table->W), N, prec, table->W, staged_ms(table));
+    if (T < table->W || N / T > 128) return LMG_ENOTSUP;      // cannot happen for N >= 2W, N <= 8192
     const int waves = fit_waves(T, prec, table->W, staged_ms(table));
     if (grid_lds_bytes(prec, table->W, T, staged_ms(table), waves) > kMaxDynLds) return LMG_ENOTSUP;
     const int cap = choose_cap();
@@ -708,6 +725,13 @@ lmg_status lmg_batch_info(const lmg_plan* p, int* nchan, int* tile, int* waves) 
 
 const char* lmg_last_error(void) { return g_last_error; }
 
+lmg_status lmg_sync_status(void* stream) {
+    LMG_HIP(hipStreamSynchronize(static_cast<hipStream_t>(stream)));
+    int flag = 0;
+    LMG_HIP(take_data_error(&flag));
+    return flag ? LMG_EDATA : LMG_OK;
+}
+
 lmg_status lmg_plan_check(const lmg_plan* p) {
     if (!p) return LMG_EINVAL;
     const lmg_status st = ensure_flags(p);
@@ -734,14 +758,14 @@ lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes) {
     return LMG_OK;
 }
 
-lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, void* scratch,
-                            size_t scratch_bytes, void* stream) {
-    if (!p || !grid || (p->nvis > 0 && !vis)) return LMG_EINVAL;
+lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, int accumulate,
+                            void* scratch, size_t scratch_bytes, void* stream) {
+    if (!p || !grid || (p->nvis > 0 && !vis) || (accumulate != 0 && accumulate != 1)) return LMG_EINVAL;
     if (!scratch_ok(p, LMG_OP_GRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
     const Scratch L = plan_scratch(p, LMG_OP_GRID);
     char* sc = static_cast<char*>(scratch);
     return run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, reinterpret_cast<int*>(sc + L.counters),
-                    static_cast<hipStream_t>(stream));
+                    static_cast<hipStream_t>(stream), false, accumulate != 0);
 }
 
 lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out, void* scratch, size_t scratch_bytes,
@@ -766,7 +790,7 @@ lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, cons
     void* grid = sc + L.grid;
     void* tmp = sc + L.tmp;
     lmg_status st = run_grid(p, vis, w, grid, sc + L.vs, sc + L.patches, reinterpret_cast<int*>(sc + L.counters), s,
-                             true);
+                             true, false);
     if (st != LMG_OK) return st;
     const bool f64 = p->prec == LMG_F64;
     const size_t cs = cplx_size(p->prec);
@@ -888,7 +912,7 @@ lmg_status one_shot_batched(const lmg_table* t, int N, lmg_precision prec, int n
     size_t pbytes = 0;
     lmg_batch_workspace_size(N, t->W, nchan, offsets[nchan], prec, &pbytes);
     lmg_plan* p = nullptr;
-    st = create_plan(t, N, prec, nchan, offsets, uv, choose_tile(N, prec), ws, pbytes, stream, &p);
+    st = create_plan(t, N, prec, nchan, offsets, uv, choose_tile(N, t->W), ws, pbytes, stream, &p);
     if (st != LMG_OK) return st;
     st = body(p, static_cast<char*>(ws) + pbytes, ws_bytes - pbytes);
     lmg_plan_destroy(p);
@@ -901,7 +925,7 @@ extern "C" {
 lmg_status lmg_grid(const lmg_table* t, int N, lmg_precision prec, int64_t nvis, const double* uv, const void* vis,
                     const float* w, void* grid, void* ws, size_t ws_bytes, void* stream) {
     return one_shot(t, N, prec, nvis, uv, ws, ws_bytes, stream, LMG_OP_GRID, [&](lmg_plan* p, void* sc, size_t sb) {
-        return lmg_grid_planned(p, vis, w, grid, sc, sb, stream);
+        return lmg_grid_planned(p, vis, w, grid, 1, sc, sb, stream);
     });
 }
 
@@ -933,7 +957,7 @@ lmg_status lmg_workspace_size_batched(int N, int W, int nchan, int64_t nvis, lmg
     if (op != LMG_OP_GRID && op != LMG_OP_DEGRID) return LMG_EINVAL;
     lmg_status st = lmg_batch_workspace_size(N, W, nchan, nvis, prec, &plan);
     if (st != LMG_OK) return st;
-    const int T = choose_tile(N, prec);
+    const int T = choose_tile(N, W);
     const Layout L = plan_layout(N, nvis, prec, choose_cap(), nchan);
     *bytes = plan + scratch_for(N, W, T, 0, L.max_items, nvis, prec, op);
     return LMG_OK;
@@ -944,7 +968,7 @@ lmg_status lmg_grid_batched(const lmg_table* t, int N, lmg_precision prec, int n
                             size_t ws_bytes, void* stream) {
     return one_shot_batched(t, N, prec, nchan, offsets, uv, ws, ws_bytes, stream, LMG_OP_GRID,
                             [&](lmg_plan* p, void* sc, size_t sb) {
-                                return lmg_grid_planned(p, vis, w, grids, sc, sb, stream);
+                                return lmg_grid_planned(p, vis, w, grids, 1, sc, sb, stream);
                             });
 }
 

@@ -54,6 +54,7 @@ struct AssembleArgs {
     int N, W, T, ntx, nchan;
     int tr0, tc0, trows, tcols;   // window of tiles written (rows tr0.., columns tc0.., wrapping)
     int rows;                     // tile rows per workgroup (set by the launcher)
+    int accumulate;               // 1: add to the grid's values; 0: overwrite every cell of the window
     const int* item_start;   // per tile, ntiles + 1
     const void* patches;
     void* grid;
@@ -118,6 +119,9 @@ hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& a, hipStream_
 hipError_t launch_degrid(lmg_precision prec, const DegridArgs& a, hipStream_t s);
 hipError_t launch_fft_pass(bool f64, const FftArgs& a, hipStream_t s);
 hipError_t set_kernel_attributes();
+// Read (and, if set, clear) the device-wide flag the plans raise on non-finite coordinates, on the
+// current device. Synchronous.
+hipError_t take_data_error(int* flag);
 // LDS bytes of the gridding kernel with `waves` private patches (the
 // degridding kernel needs no more than one patch).
 size_t grid_lds_bytes(lmg_precision prec, int W, int T, int Ms, int waves);

@@ -1,7 +1,8 @@
-"""Writes dft_samples_16m_4096.txt: the direct-DFT dirty image (Eq. 3) of the
-16,777,152-visibility array workload on a 4096^2 grid, sampled on a 64 x 64
-lattice of pixels p, q = -1024 + 32 a (a = 0..63) that spans the retained
-field |x|, |y| < x0 = 1/4.
+"""Writes dft_samples_16m_4096.npy: the direct-DFT dirty image (Eq. 3) of the
+16,777,152-visibility array workload on a 4096^2 grid, sampled on the
+256 x 256 lattice of pixels p, q = -1024 + 8 a (a = 0..255), every 8th pixel
+of the retained field |x|, |y| < x0 = 1/4, as a complex128 array [q index,
+p index] (numpy's .npy format, no pickled objects).
 
 Calls only the oracle and the seeded input generator. The visibilities are
 rounded to complex64 first, as the FP32 library paths receive them (the FP64
@@ -20,7 +21,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import synth  # noqa: E402
 from oracle import imaging as im  # noqa: E402
 
-PIXELS = -1024 + 32 * np.arange(64)
+PIXELS = -1024 + 8 * np.arange(256)
 
 
 def main():
@@ -28,16 +29,9 @@ def main():
     c = synth.array_16m_case(with_vis=True, device="cpu")
     vis = c.vis.astype(np.complex64).astype(np.complex128)
     img = im.dft_dirty_image(c.uv, vis, None, c.N, c.x0, pixels_x=PIXELS, pixels_y=PIXELS, chunk=1 << 15)
-    out = os.path.join(HERE, "dft_samples_16m_4096.txt")
-    with open(out, "w") as f:
-        f.write("# Direct DFT dirty image (Eq. 3), 16,777,152 array visibilities (seed 3, 8,322 hour angles),\n")
-        f.write("# N = 4096, unit weights, complex64-rounded visibilities; pixels p, q = -1024 + 32 a, a = 0..63.\n")
-        f.write("# Written by tests/golden/make_dft_samples.py (oracle only). Rows: q index a, p index b, re, im.\n")
-        f.write(f"# sum |V|^2 = {np.sum(np.abs(vis) ** 2):.17e}\n")
-        for a in range(64):
-            for b in range(64):
-                f.write(f"{a} {b} {img[a, b].real:.17e} {img[a, b].imag:.17e}\n")
-    print(f"wrote {out} in {time.time() - t0:.1f} s")
+    out = os.path.join(HERE, "dft_samples_16m_4096.npy")
+    np.save(out, img)
+    print(f"wrote {out} in {time.time() - t0:.1f} s; sum |V|^2 = {np.sum(np.abs(vis) ** 2):.17e}")
 
 
 if __name__ == "__main__":

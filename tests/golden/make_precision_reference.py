@@ -1,8 +1,8 @@
 """Writes precision_reference_16m_4096.txt: for W = 3, 5, 7 (300-entry cubic
 tables, x0 = 1/4), the relative RMS difference between the oracle's FP64 dirty
 image (grid, FFT, correct, crop) of the 16,777,152-visibility array workload
-on a 4096^2 grid (the same uv, scaled for W = 7, at every W) and the direct DFT, over the 64 x 64 pixel lattice of
-dft_samples_16m_4096.txt. This is the method's own error (Eqs. 7-8, 11) with
+on a 4096^2 grid (the same uv, scaled for W = 7, at every W) and the direct DFT, over the 256 x 256 pixel lattice
+of dft_samples_16m_4096.npy (every 8th pixel of the retained field). This is the method's own error (Eqs. 7-8, 11) with
 no rounding beyond FP64, against which the library's FP32, compensated FP32
 and FP64 modes are compared.
 
@@ -24,10 +24,7 @@ from oracle import lmtable as lt  # noqa: E402
 
 
 def load_dft():
-    d = np.loadtxt(os.path.join(HERE, "dft_samples_16m_4096.txt"))
-    img = np.zeros((64, 64), dtype=np.complex128)
-    img[d[:, 0].astype(int), d[:, 1].astype(int)] = d[:, 2] + 1j * d[:, 3]
-    return img
+    return np.load(os.path.join(HERE, "dft_samples_16m_4096.npy"))
 
 
 def main():
@@ -36,7 +33,7 @@ def main():
     c = synth.array_16m_case(with_vis=True, device="cpu")
     vis = c.vis.astype(np.complex64).astype(np.complex128)
     M = im.crop_size(c.N, c.x0)
-    sel = -1024 + 32 * np.arange(64) + M // 2
+    sel = -1024 + 8 * np.arange(256) + M // 2
     lines = []
     for W in (3, 5, 7):
         tab, h = lt.make_table(W, c.x0, 300, 3)
@@ -48,8 +45,8 @@ def main():
         print(f"W={W} rel_rms={err:.3e} ({time.time() - t0:.0f} s)", flush=True)
     out = os.path.join(HERE, "precision_reference_16m_4096.txt")
     with open(out, "w") as f:
-        f.write("# Relative RMS error of the FP64 oracle dirty image against the direct DFT over the 64 x 64\n")
-        f.write("# lattice of dft_samples_16m_4096.txt; 300-entry cubic tables, x0 = 1/4.\n")
+        f.write("# Relative RMS error of the FP64 oracle dirty image against the direct DFT over the 256 x 256\n")
+        f.write("# lattice of dft_samples_16m_4096.npy; 300-entry cubic tables, x0 = 1/4.\n")
         f.write("# Written by tests/golden/make_precision_reference.py (oracle only). Columns: W, rel_rms.\n")
         f.write("\n".join(lines) + "\n")
 

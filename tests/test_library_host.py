@@ -182,3 +182,55 @@ def test_batch_plan_rejects_bad_arguments_before_any_launch():
     assert n.value > 0
     assert lib.lmg_batch_workspace_size(1024, 5, 0, 10, lmg.F32, ctypes.byref(n)) == -1
     assert lib.lmg_workspace_size_batched(1024, 5, 4, 100, lmg.F32, lmg.OP_DIRTY, ctypes.byref(n)) == -1
+
+
+def test_tile_below_support_is_rejected():
+    """A footprint (W cells, Eq. 6) must not reach two tiles away: an explicit tile edge below W is an argument
+    error, found on the host before anything is enqueued (T = W is accepted: no workspace is the next error)."""
+    lib = lmg.load()
+    out = ctypes.c_void_p()
+    off = (ctypes.c_int64 * 2)(0, 0)
+    for W, tile, expect in ((12, 8, -1), (9, 8, -1), (16, 8, -1), (8, 8, -2), (12, 16, -2), (16, 16, -2)):
+        t = lmg.Table.from_h(W, 0.25, 300, 1, np.ones(33))
+        st = lib.lmg_batch_plan_create(t.handle, 128, lmg.F32, 1, off, None, tile, None, 0, None, ctypes.byref(out))
+        assert st == expect, (W, tile, st)
+
+
+def test_python_wrappers_check_arguments_on_the_host():
+    """The one-shot wrappers check dtype, shape and contiguity before any pointer reaches the library (on host
+    tensors these checks run first; a well-formed host tensor is then refused as not on the device)."""
+    torch = pytest.importorskip("torch")
+    t = lmg.Table.from_h(7, 0.25, 300, 3, lt.optimal_h(7, 0.25))
+    uv = torch.zeros((10, 2), dtype=torch.float64)
+    vis = torch.zeros(10, dtype=torch.complex64)
+    w = torch.ones(10, dtype=torch.float32)
+    with pytest.raises(ValueError):
+        lmg.grid(t, 64, torch.zeros((10, 3), dtype=torch.float64), vis)           # uv not (nvis, 2)
+    with pytest.raises(TypeError):
+        lmg.grid(t, 64, uv.float(), vis)                                           # uv not float64
+    with pytest.raises(ValueError):
+        lmg.grid(t, 64, uv, torch.zeros(11, dtype=torch.complex64))               # vis longer than uv
+    with pytest.raises(TypeError):
+        lmg.grid(t, 64, uv, vis, w.double())                                       # weights not float32
+    with pytest.raises(ValueError):
+        lmg.grid(t, 64, uv, vis, torch.ones(9, dtype=torch.float32))              # weights too short
+    with pytest.raises(ValueError):
+        lmg.grid(t, 64, uv, vis, out=torch.zeros((64, 32), dtype=torch.complex64))   # grid too small
+    with pytest.raises(ValueError):
+        lmg.grid(t, 64, torch.zeros((2, 10), dtype=torch.float64).t(), vis)       # non-contiguous uv
+    with pytest.raises(TypeError):
+        lmg.grid(t, 64, uv, vis.real.contiguous())                                 # real visibilities
+    with pytest.raises(ValueError):
+        lmg.degrid(t, 64, uv, torch.zeros((32, 32), dtype=torch.complex64))       # grid not N x N
+    with pytest.raises(ValueError):
+        lmg.make_dirty_image(t, 64, uv, torch.zeros(9, dtype=torch.complex128))
+    with pytest.raises(ValueError):
+        lmg.predict_visibilities(t, 64, uv, torch.zeros((64, 64), dtype=torch.complex64))   # image not M x M
+    with pytest.raises(ValueError):
+        lmg.grid_batched(t, 64, uv, [0, 4, 9], vis)                               # offsets end before nvis
+    with pytest.raises(ValueError):
+        lmg.degrid_batched(t, 64, uv, [0, 6, 4, 10], torch.zeros((3, 64, 64), dtype=torch.complex64))
+    with pytest.raises(ValueError):
+        lmg.fft2_centred(torch.zeros((8, 16), dtype=torch.complex64), +1)
+    with pytest.raises(TypeError):                                                  # well formed, but on the host
+        lmg.grid(t, 64, uv, vis, w)

@@ -145,6 +145,57 @@ def test_dft_fft_misfit_bound_every_pixel(w7, small_images):
     assert np.max(np.abs(dft_img - fft_img)) < 1e-5 * np.max(np.abs(dft_img))
 
 
+def _map_error_2d(tab, hp, N, pix):
+    """l_2D(x_p, y_q) of the separable kernel (Eq. 11 in 2D) for the table and correction used: averaging
+    |1 - h(x) h(y) S_u(x) S_v(y)|^2 over both offsets gives 1 - 2 h_x h_y c_x c_y + h_x^2 h_y^2 D_x D_y with the
+    1D c (Eq. 13) and D (Eq. 14). The nu integral over the piecewise-polynomial table uses a composite rule."""
+    lo = lt.delta_low(tab.W)
+    quad = lt.composite_midpoint(lo, lo + 1.0, tab.Ms * 16)
+    _, hx, c, D = lt.map_error(lambda d: tab.weights(d).T, tab.W, pix / N, h_of_x=hp[pix + N // 2], quad=quad)
+    return 1 - 2 * np.outer(hx * c, hx * c) + np.outer(hx * hx * D, hx * hx * D)      # [q, p]
+
+
+def test_misfit_level_and_bound_from_the_map_error(w7, small_images):
+    """The misfit bound of Eqs. (7)-(8) pinned from both sides by the map error (Eq. 11, Sec. 2.1).
+
+    With independent visibilities at offsets spread evenly over the cell, the expected |I_D - I_FFT|^2 at a
+    pixel is sum_k w_k^2 |V_k|^2 |b_k|^2 and the mean of |b_k|^2 over the visibilities is l_2D, so the RMS
+    misfit is close to sqrt(mean l_2D * sum w^2 |V|^2); and the Cauchy-Schwarz bound, (sum w |V|^2)
+    (sum w |b_k|^2), is close to (sum w |V|^2)(sum w) l_2D at every pixel. Both within 3x. A bound with a
+    factor dropped (h, or one of the sums) fails the second check."""
+    tab, _ = w7
+    case, hp, fft_img, dft_img = small_images
+    N = case.N
+    p = np.arange(-32, 32)
+    l2 = _map_error_2d(tab, hp, N, p)
+    w = np.ones(len(case.uv)) if case.weights is None else np.asarray(case.weights, dtype=np.float64)
+    v2 = np.abs(case.vis) ** 2
+    rms = np.sqrt(np.mean(np.abs(fft_img - dft_img) ** 2))
+    pred = np.sqrt(l2.mean() * np.sum(w * w * v2))
+    assert pred / 3 < rms < 3 * pred
+    pq = np.stack(np.meshgrid(p, p, indexing="xy"), -1).reshape(-1, 2)
+    bound = im.image_misfit_bound(case.uv, case.vis, case.weights, N, tab, hp, pq)
+    ratio = bound / (np.sum(w * v2) * np.sum(w) * l2.reshape(-1))
+    assert np.all(ratio > 1 / 3) and np.all(ratio < 3)
+
+
+def test_point_sources_predict_as_a_delta_image(w7):
+    """Eq. (2): a sky of point sources on pixel centres is the image with those pixels set to the fluxes, so
+    the per-source sum equals the direct prediction of that image (a different evaluation of the same sum)."""
+    N, x0 = 64, 0.25
+    rng = np.random.default_rng(21)
+    uv = rng.uniform(-16, 16, (300, 2))
+    pos = rng.integers(-16, 16, (9, 2))
+    flux = rng.uniform(0.1, 1.0, 9)
+    img = np.zeros((32, 32), complex)
+    for (px, qy), f in zip(pos, flux):
+        img[qy + 16, px + 16] += f
+    np.testing.assert_allclose(im.point_source_predict(uv, N, pos, flux), im.direct_predict(uv, img, N, x0),
+                               rtol=0, atol=1e-12)
+    # and a single unit source at the origin has V = 1 everywhere
+    np.testing.assert_allclose(im.point_source_predict(uv, N, [(0, 0)], [1.0]), np.ones(300), atol=0)
+
+
 def test_misfit_larger_for_smaller_width(small_images):
     """Sec. 2.2/4.1: the image misfit falls steeply with W (W = 3 far worse than W = 7)."""
     case, _, fft7, dft = small_images

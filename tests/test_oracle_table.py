@@ -78,18 +78,49 @@ def test_map_error_identity_at_optimum():
 def test_w7_reaches_single_precision_level():
     """Secs. 2.2 and 3: at W = 7, x0 = 0.25 the map error over |x| <= x0 is of order 1e-14.
 
-    Reading: the level holds for the bulk of the field (median and
-    mean near 1e-14); the function rises towards 2e-13 at the very edge x = x0.
+    Reading: the optimiser minimises E, the mean of l over the field (Eq. 16),
+    and that minimum is 1.46-1.49e-14 under every fair reading of App. A tried
+    (N_g = 32 or 64, M_g = 16 or 32); since max l >= mean l, no reading puts l
+    below 1e-14 over the whole field, so the printed "less than 1e-14" is an
+    order of magnitude (the same paragraph says l "at" 1e-14). Pinned here to
+    the level the optimum reaches, tightly enough that an optimiser stopping at
+    twice the minimal E fails: E and the mean of l within [1, 2] x 1e-14, the
+    median below 1.5e-14, the edge value l(x0) (the maximum, 1.83e-13) below
+    2.5e-13.
     """
     level = paper_value("ell_level_W7_x0_0.25")
     x = np.linspace(0.0, 0.25, 501)
     ell, _, _, _ = true_ell(7, 0.25, x)
-    assert level / 10 < np.median(ell) < 3 * level
-    assert level / 10 < ell.mean() < 3 * level
-    assert ell.max() < 1e-12                         # still below the FP32 limit squared
+    E = lt.integrated_misfit_coarse(lt.optimal_h(7, 0.25), 7, 0.25)
+    assert level < E < 2 * level
+    assert level < ell.mean() < 2 * level
+    assert level / 10 < np.median(ell) < 1.5 * level
+    assert ell.max() == ell[-1] and ell.max() < 2.5e-13
     # W = 6 does not reach that level; W = 8 goes well below it (Sec. 2.2: W = 7 is the smallest choice)
     ell6, _, _, _ = true_ell(6, 0.25, x)
     assert np.median(ell6) > 10 * level
+
+
+def test_w7_optimum_is_a_local_minimum_of_E():
+    """App. A: h minimises E. At the optimiser's h, moving the 32 free samples by a relative 1e-8 along random
+    directions raises E by the same amount in both senses (no first-order term: the gradient vanishes). An h
+    with twice the minimal E has a gradient whose first-order change (~2.6e-2 E here) would swamp the
+    second-order rise (~1.7e-4 E) and lower E on one side."""
+    W, x0 = 7, 0.25
+    h = lt.optimal_h(W, x0)
+    E0 = lt.integrated_misfit_coarse(h, W, x0)
+    rng = np.random.default_rng(17)
+    eps = 1e-8
+    for _ in range(6):
+        d = rng.standard_normal(32)
+        d /= np.linalg.norm(d)
+        up, dn = h.copy(), h.copy()
+        up[1:] *= 1 + eps * d
+        dn[1:] *= 1 - eps * d
+        rp = lt.integrated_misfit_coarse(up, W, x0) / E0 - 1
+        rm = lt.integrated_misfit_coarse(dn, W, x0) / E0 - 1
+        assert rp > 1e-6 and rm > 1e-6
+        assert abs(rp - rm) < 0.05 * (rp + rm)
 
 
 def test_misfit_falls_with_width_and_with_x0():
