@@ -199,6 +199,24 @@ lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes);
 lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, int accumulate,
                             void* scratch, size_t scratch_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * lmg_grid_planned with its scratch taken from a fixed device array of
+ * LMG_STATIC_SCRATCH_BYTES (64 MiB) that the library holds on each device it
+ * runs on until the process ends, instead of a caller workspace. Same
+ * arguments and results as lmg_grid_planned (accumulate 0 or 1). It calls no
+ * hipMalloc, hipFree or allocating library routine; the first call on a
+ * device looks up the array's address there. LMG_ENOTSUP, with nothing
+ * enqueued, when the plan's gridding scratch (lmg_plan_scratch_size with
+ * LMG_OP_GRID) exceeds the array. Every call on a device shares that
+ * device's array, which keeps the previous call's contents (the call
+ * initialises what it reads): calls that overlap in time on one device
+ * (different streams or host threads) race and give wrong grids, so
+ * serialise them, for example on one stream. */
+#define LMG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+lmg_status lmg_grid_planned_noalloc(const lmg_plan* p, const void* vis, const float* w, void* grid, int accumulate,
+                                    void* stream);
+
 /* Degridding, the transpose of gridding (Sec. 1, Sec. 5):
  * vis_out[k] = sum_{m,n} C(m - v_k) C(n - u_k) grid[m][n]. Weights do not
  * apply. vis_out: device complex (nvis), overwritten. */

@@ -88,6 +88,7 @@ def load():
         "lmg_plan_destroy": (None, [P]),
         "lmg_plan_scratch_size": (I, [P, I, PZ]),
         "lmg_grid_planned": (I, [P, P, P, P, I, P, Z, P]),
+        "lmg_grid_planned_noalloc": (I, [P, P, P, P, I, P]),
         "lmg_degrid_planned": (I, [P, P, P, P, Z, P]),
         "lmg_make_dirty_image_planned": (I, [P, P, P, P, P, Z, P]),
         "lmg_predict_visibilities_planned": (I, [P, P, P, P, Z, P]),
@@ -376,6 +377,23 @@ class Plan:
         sc = self.scratch(OP_GRID)
         _check(self.lib.lmg_grid_planned(self._h, _ptr(vis), _ptr(weights), _ptr(out), 1 if accumulate else 0,
                                          _ptr(sc), sc.numel(), _stream_handle(stream)), "lmg_grid_planned")
+        return out
+
+    def grid_noalloc(self, vis, weights=None, out=None, accumulate: bool = False, stream=None):
+        """Gridding with no device allocation by the library (lmg_grid_planned_noalloc): the scratch is the
+        library's fixed per-device array; calls overlapping on one device race. ``out`` must be given when
+        accumulating; otherwise a grid is allocated here (by torch) if it is missing."""
+        torch = _torch()
+        _check_tensor(vis, "vis", self._vis_dtype(), (self.nvis,), self.device)
+        if weights is not None:
+            _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs an output grid")
+            out = torch.empty(self.grid_shape, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "grid", self._vis_dtype(), self.grid_shape, self.device)
+        _check(self.lib.lmg_grid_planned_noalloc(self._h, _ptr(vis), _ptr(weights), _ptr(out), 1 if accumulate else 0,
+                                                 _stream_handle(stream)), "lmg_grid_planned_noalloc")
         return out
 
     def degrid(self, grid, out=None, stream=None):
