@@ -280,13 +280,11 @@ def _timed(fn, reps, stream=None):
 
 def precision_study(lmg, case, uv, vis64, reps=5):
     """Dirty images of the workload for W = 3, 5, 7 in the three accumulation modes against the direct DFT on
-    the 64 x 64 pixel lattice of tests/golden/dft_samples_16m_4096.txt; with the time of one dirty image +
+    the 256 x 256 pixel lattice (every 8th pixel of the retained field) of tests/golden/dft_samples_16m_4096.npy; with the time of one dirty image +
     prediction (plan reused). The compensated FP32 mode goes through the autograd wrappers."""
     import torch
-    d = np.loadtxt(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.txt"))
-    dft = np.zeros((64, 64), dtype=np.complex128)
-    dft[d[:, 0].astype(int), d[:, 1].astype(int)] = d[:, 2] + 1j * d[:, 3]
-    pix = -1024 + 32 * np.arange(64)
+    dft = np.load(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.npy"))
+    pix = -1024 + 8 * np.arange(256)
     rows = []
     for W in (3, 5, 7):
         table = lmg.Table.create(W, case.x0, case.table_size, case.degree)
@@ -310,7 +308,8 @@ def precision_study(lmg, case, uv, vis64, reps=5):
         "rows": rows,
         "speedup_kahan_over_f64_W7": round(t[(7, "f64")]["ms_dirty_plus_predict"] /
                                            t[(7, "kahan")]["ms_dirty_plus_predict"], 3),
-        "note": "error = relative RMS against the FP64 direct DFT (Eq. 3) on a 64 x 64 pixel lattice; "
+        "note": "error = relative RMS against the FP64 direct DFT (Eq. 3) on the 256 x 256 lattice of every 8th "
+                "pixel of the retained field; "
                 "time = make_dirty_image + predict_visibilities with the plan reused; the compensated mode "
                 "runs through the autograd wrappers",
     }
@@ -327,10 +326,8 @@ def direct_study(lmg, case, uv, vis64, reps=5):
     direct DFT in the three modes for W = 5 and 7, the time of one dirty image + prediction (plan reused),
     and the gridding kernel's FP64 rate (it is bound by the weights' arithmetic)."""
     import torch
-    d = np.loadtxt(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.txt"))
-    dft = np.zeros((64, 64), dtype=np.complex128)
-    dft[d[:, 0].astype(int), d[:, 1].astype(int)] = d[:, 2] + 1j * d[:, 3]
-    pix = -1024 + 32 * np.arange(64)
+    dft = np.load(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.npy"))
+    pix = -1024 + 8 * np.arange(256)
     nvis = uv.shape[0]
     rows = []
     for W in (5, 7):
