@@ -547,6 +547,29 @@ def main():
     torch.cuda.synchronize()
     ms_reuse = (time.perf_counter() - r0) * 1e3 / args.steps
 
+    # The unit of work the metric names: one visibility gridded (lmg_grid_planned, overwriting the 4096^2
+    # grid) and degridded (lmg_degrid_planned) with the plan reused, data in caller order (two reorderings
+    # per pair of calls); and the same pair on data kept in the plan's order (lmg_*_planned_ordered).
+    gu = torch.empty((N, N), dtype=cdt, device=dev)
+    vu = torch.empty(nvis, dtype=cdt, device=dev)
+    vp = plan.to_plan_order(vis, w)
+    vpo = torch.zeros_like(vp)
+    ms_unit_caller = _timed(lambda: (plan.grid(vis, w, out=gu), plan.degrid(gu, out=vu)), args.steps)
+    ms_unit_plan = _timed(lambda: (plan.grid_ordered(vp, out=gu), plan.degrid_ordered(gu, out=vpo)), args.steps)
+    unit_bytes = (16.0 + cs + 4.0) * nvis + (16.0 + cs) * nvis + 2.0 * N * N * cs
+    grid_degrid_unit = {
+        "ms_caller_order": round(ms_unit_caller, 4), "vis_per_s_caller_order": nvis / (ms_unit_caller * 1e-3),
+        "ms_plan_order": round(ms_unit_plan, 4), "vis_per_s_plan_order": nvis / (ms_unit_plan * 1e-3),
+        "algorithmic_bytes_per_vis": round(unit_bytes / nvis, 2),
+        "hbm_frac_caller_order": round(unit_bytes / (ms_unit_caller * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "hbm_frac_plan_order": round(unit_bytes / (ms_unit_plan * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "note": "lmg_grid_planned + lmg_degrid_planned on the 4096^2 grid, plan reused (HIP events, mean of "
+                "--steps); plan order = data kept in the plan's order (lmg_to_plan_order once), no reordering",
+    }
+    print(f"# unit: caller order {ms_unit_caller:.3f} ms, plan order {ms_unit_plan:.3f} ms", file=sys.stderr,
+          flush=True)
+    del gu, vu, vp, vpo
+
     kernels = {}
     for name, (n, tot) in trace.items():
         avg = tot / n
@@ -590,6 +613,7 @@ def main():
         },
         "roofline": roofline,
         "kernels": kernels,
+        "grid_degrid_unit": grid_degrid_unit,
         "value_plan_reused": nvis / (ms_reuse * 1e-3),
         "ms_per_step_plan_reused": round(ms_reuse, 4),
         "source_hash": kernel_source_hash(),

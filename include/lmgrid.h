@@ -223,6 +223,31 @@ lmg_status lmg_grid_planned_noalloc(const lmg_plan* p, const void* vis, const fl
 lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out,
                               void* scratch, size_t scratch_bytes, void* stream);
 
+/* ------------------------------------------------------ calls in plan order
+ * A plan grids visibilities in its own order ("plan order": by uv tile, then
+ * footprint cell), and the planned calls above reorder the caller's arrays on
+ * the way in (lmg_grid_planned) and out (lmg_degrid_planned). Iterative
+ * imaging (major cycles: predict, subtract, grid the residuals; gradient
+ * steps) can keep its visibility data in plan order instead, reorder once, and
+ * skip both passes in every call. A plan-ordered array holds
+ * lmg_plan_order_length elements (nvis plus padding that the kernels may read
+ * and never write), of the plan's complex type; visibilities dropped for
+ * non-finite coordinates have no element. */
+lmg_status lmg_plan_order_length(const lmg_plan* p, int64_t* n);
+/* vis_plan = w V in plan order (w: device float32 (nvis) or NULL for unit
+ * weights; vis: device complex (nvis), caller order). */
+lmg_status lmg_to_plan_order(const lmg_plan* p, const void* vis, const float* w, void* vis_plan, void* stream);
+/* vis = the caller-order copy of vis_plan (zero for dropped visibilities). */
+lmg_status lmg_from_plan_order(const lmg_plan* p, const void* vis_plan, void* vis, void* stream);
+/* lmg_grid_planned and lmg_degrid_planned on plan-ordered data (weights
+ * already applied by lmg_to_plan_order); same grids and visibilities, bit for
+ * bit, as the caller-order calls give after reordering. Scratch: the sizes
+ * lmg_plan_scratch_size returns for LMG_OP_GRID and LMG_OP_DEGRID. */
+lmg_status lmg_grid_planned_ordered(const lmg_plan* p, const void* vis_plan, void* grid, int accumulate,
+                                    void* scratch, size_t scratch_bytes, void* stream);
+lmg_status lmg_degrid_planned_ordered(const lmg_plan* p, const void* grid, void* vis_plan_out, void* scratch,
+                                      size_t scratch_bytes, void* stream);
+
 /* Dirty image (Eq. 4 in 2D): grid, inverse 2D FFT (exponent +i2pi), multiply
  * by h(x_p) h(y_q) and keep |x|, |y| <= x0. image: device complex
  * (2 x0 N)^2, overwritten. No normalisation by sum(w). The transforms are

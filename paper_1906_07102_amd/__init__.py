@@ -90,6 +90,11 @@ def load():
         "lmg_grid_planned": (I, [P, P, P, P, I, P, Z, P]),
         "lmg_grid_planned_noalloc": (I, [P, P, P, P, I, P]),
         "lmg_degrid_planned": (I, [P, P, P, P, Z, P]),
+        "lmg_plan_order_length": (I, [P, ctypes.POINTER(I64)]),
+        "lmg_to_plan_order": (I, [P, P, P, P, P]),
+        "lmg_from_plan_order": (I, [P, P, P, P]),
+        "lmg_grid_planned_ordered": (I, [P, P, P, I, P, Z, P]),
+        "lmg_degrid_planned_ordered": (I, [P, P, P, P, Z, P]),
         "lmg_make_dirty_image_planned": (I, [P, P, P, P, P, Z, P]),
         "lmg_predict_visibilities_planned": (I, [P, P, P, P, Z, P]),
         "lmg_workspace_size": (I, [I, I, D, I64, I, I, PZ]),
@@ -405,6 +410,65 @@ class Plan:
         sc = self.scratch(OP_DEGRID)
         _check(self.lib.lmg_degrid_planned(self._h, _ptr(grid), _ptr(out), _ptr(sc), sc.numel(),
                                            _stream_handle(stream)), "lmg_degrid_planned")
+        return out
+
+    # ---- plan order: keep visibility data in the plan's own order across calls (no reordering per call)
+    def plan_order_length(self) -> int:
+        n = ctypes.c_int64()
+        _check(self.lib.lmg_plan_order_length(self._h, ctypes.byref(n)), "lmg_plan_order_length")
+        return n.value
+
+    def to_plan_order(self, vis, weights=None, out=None, stream=None):
+        """w V in plan order (lmg_to_plan_order): a tensor of plan_order_length() elements."""
+        torch = _torch()
+        _check_tensor(vis, "vis", self._vis_dtype(), (self.nvis,), self.device)
+        if weights is not None:
+            _check_tensor(weights, "weights", torch.float32, (self.nvis,), self.device)
+        n = self.plan_order_length()
+        if out is None:
+            out = torch.zeros(n, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "vis_plan", self._vis_dtype(), (n,), self.device)
+        _check(self.lib.lmg_to_plan_order(self._h, _ptr(vis), _ptr(weights), _ptr(out), _stream_handle(stream)),
+               "lmg_to_plan_order")
+        return out
+
+    def from_plan_order(self, vis_plan, out=None, stream=None):
+        """Caller-order copy of plan-ordered visibilities (lmg_from_plan_order)."""
+        torch = _torch()
+        _check_tensor(vis_plan, "vis_plan", self._vis_dtype(), (self.plan_order_length(),), self.device)
+        if out is None:
+            out = torch.empty(self.nvis, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "vis", self._vis_dtype(), (self.nvis,), self.device)
+        _check(self.lib.lmg_from_plan_order(self._h, _ptr(vis_plan), _ptr(out), _stream_handle(stream)),
+               "lmg_from_plan_order")
+        return out
+
+    def grid_ordered(self, vis_plan, out=None, accumulate: bool = False, stream=None):
+        """Gridding of plan-ordered visibilities (lmg_grid_planned_ordered)."""
+        torch = _torch()
+        _check_tensor(vis_plan, "vis_plan", self._vis_dtype(), (self.plan_order_length(),), self.device)
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs an output grid")
+            out = torch.empty(self.grid_shape, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "grid", self._vis_dtype(), self.grid_shape, self.device)
+        sc = self.scratch(OP_GRID)
+        _check(self.lib.lmg_grid_planned_ordered(self._h, _ptr(vis_plan), _ptr(out), 1 if accumulate else 0,
+                                                 _ptr(sc), sc.numel(), _stream_handle(stream)),
+               "lmg_grid_planned_ordered")
+        return out
+
+    def degrid_ordered(self, grid, out=None, stream=None):
+        """Degridding into plan order (lmg_degrid_planned_ordered)."""
+        torch = _torch()
+        _check_tensor(grid, "grid", self._vis_dtype(), self.grid_shape, self.device)
+        n = self.plan_order_length()
+        if out is None:
+            out = torch.zeros(n, dtype=self._vis_dtype(), device=self.device)
+        _check_tensor(out, "vis_plan", self._vis_dtype(), (n,), self.device)
+        sc = self.scratch(OP_DEGRID)
+        _check(self.lib.lmg_degrid_planned_ordered(self._h, _ptr(grid), _ptr(out), _ptr(sc), sc.numel(),
+                                                   _stream_handle(stream)), "lmg_degrid_planned_ordered")
         return out
 
     def make_dirty_image(self, vis, weights=None, out=None, stream=None):

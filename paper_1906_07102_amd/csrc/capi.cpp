@@ -443,18 +443,14 @@ lmg_status wait_plan(const lmg_plan* p, hipStream_t s) {
     return LMG_OK;
 }
 
-// Gridding through the plan: overwrite the grid (every cell of the window
-// written), or add to it (accumulate: only tiles that receive patches are
-// read and written).
-lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
-                    int* counters, hipStream_t s, bool band_only, bool accumulate) {
+// Gridding of visibilities already in entry order (weights applied) through
+// the plan: overwrite the grid (every cell of the window written), or add to
+// it (accumulate: only tiles that receive patches are read and written).
+lmg_status run_grid_entries(const lmg_plan* p, const void* vs, void* grid, void* patches, int* counters, hipStream_t s,
+                            bool band_only, bool accumulate) {
     const lmg_table* t = p->table;
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
-    LMG_HIP(launch_zero_ints(counters, kCounters, s));
-    {
-        TraceScope ts("permute_in", s);
-        LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vs, s));
-    }
+    LMG_HIP(launch_zero_ints(counters, 1, s));
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = staged_ms(t); a.degree = kernel_degree(t);
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.F = p->F;
@@ -480,7 +476,19 @@ lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* gr
     return LMG_OK;
 }
 
-lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, int* counters, hipStream_t s) {
+// Caller order -> entry order (vs = w V), then gridding.
+lmg_status run_grid(const lmg_plan* p, const void* vis, const float* w, void* grid, void* vs, void* patches,
+                    int* counters, hipStream_t s, bool band_only, bool accumulate) {
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
+    {
+        TraceScope ts("permute_in", s);
+        LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vs, s));
+    }
+    return run_grid_entries(p, vs, grid, patches, counters, s, band_only, accumulate);
+}
+
+// Degridding into entry order.
+lmg_status run_degrid_entries(const lmg_plan* p, const void* grid, void* vs, int* counters, hipStream_t s) {
     const lmg_table* t = p->table;
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters + 1, 1, s));
@@ -489,10 +497,15 @@ lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* 
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
-    {
-        TraceScope ts("degrid_items", s);
-        LMG_HIP(launch_degrid(p->prec, a, s));
-    }
+    TraceScope ts("degrid_items", s);
+    LMG_HIP(launch_degrid(p->prec, a, s));
+    return LMG_OK;
+}
+
+// Degridding, then entry order -> caller order.
+lmg_status run_degrid(const lmg_plan* p, const void* grid, void* vis_out, void* vs, int* counters, hipStream_t s) {
+    const lmg_status st = run_degrid_entries(p, grid, vs, counters, s);
+    if (st != LMG_OK) return st;
     TraceScope ts("permute_out", s);
     LMG_HIP(launch_permute_out(p->prec == LMG_F64, vs, p->inv, p->nvis, vis_out, s));
     return LMG_OK;
@@ -776,6 +789,50 @@ lmg_status lmg_degrid_planned(const lmg_plan* p, const void* grid, void* vis_out
     char* sc = static_cast<char*>(scratch);
     return run_degrid(p, grid, vis_out, sc + L.vs, reinterpret_cast<int*>(sc + L.counters),
                       static_cast<hipStream_t>(stream));
+}
+
+lmg_status lmg_plan_order_length(const lmg_plan* p, int64_t* n) {
+    if (!p || !n) return LMG_EINVAL;
+    *n = p->nvis + kRunPad;
+    return LMG_OK;
+}
+
+lmg_status lmg_to_plan_order(const lmg_plan* p, const void* vis, const float* w, void* vis_plan, void* stream) {
+    if (!p || (p->nvis > 0 && (!vis || !vis_plan))) return LMG_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
+    TraceScope ts("permute_in", s);
+    LMG_HIP(launch_permute_in(p->prec == LMG_F64, vis, w, p->inv, p->nvis, vis_plan, s));
+    return LMG_OK;
+}
+
+lmg_status lmg_from_plan_order(const lmg_plan* p, const void* vis_plan, void* vis, void* stream) {
+    if (!p || (p->nvis > 0 && (!vis || !vis_plan))) return LMG_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
+    TraceScope ts("permute_out", s);
+    LMG_HIP(launch_permute_out(p->prec == LMG_F64, vis_plan, p->inv, p->nvis, vis, s));
+    return LMG_OK;
+}
+
+lmg_status lmg_grid_planned_ordered(const lmg_plan* p, const void* vis_plan, void* grid, int accumulate, void* scratch,
+                                    size_t scratch_bytes, void* stream) {
+    if (!p || !grid || (p->nvis > 0 && !vis_plan) || (accumulate != 0 && accumulate != 1)) return LMG_EINVAL;
+    if (!scratch_ok(p, LMG_OP_GRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    const Scratch L = plan_scratch(p, LMG_OP_GRID);
+    char* sc = static_cast<char*>(scratch);
+    return run_grid_entries(p, vis_plan, grid, sc + L.patches, reinterpret_cast<int*>(sc + L.counters),
+                            static_cast<hipStream_t>(stream), false, accumulate != 0);
+}
+
+lmg_status lmg_degrid_planned_ordered(const lmg_plan* p, const void* grid, void* vis_plan_out, void* scratch,
+                                      size_t scratch_bytes, void* stream) {
+    if (!p || !grid || (p->nvis > 0 && !vis_plan_out)) return LMG_EINVAL;
+    if (!scratch_ok(p, LMG_OP_DEGRID, scratch, scratch_bytes)) return LMG_EWORKSPACE;
+    const Scratch L = plan_scratch(p, LMG_OP_DEGRID);
+    char* sc = static_cast<char*>(scratch);
+    return run_degrid_entries(p, grid, vis_plan_out, reinterpret_cast<int*>(sc + L.counters),
+                              static_cast<hipStream_t>(stream));
 }
 
 lmg_status lmg_make_dirty_image_planned(const lmg_plan* p, const void* vis, const float* w, void* image, void* scratch,

@@ -30,8 +30,10 @@ hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& args, hipStre
     // workgroups, for balance); about 1,024 cells when it has many, as in a batched plan's full grids of
     // mostly empty tiles, where smaller workgroups make the write bound by workgroup dispatch.
     AssembleArgs a = args;
+    // A whole grid of one channel (tiles of mostly empty cells) is also written whole tiles at a time.
     const int64_t tiles = static_cast<int64_t>(a.nchan) * a.trows * a.tcols;
-    a.rows = tiles > 32768 ? std::min(a.T, 1024 / a.T) : std::min(a.T, 8);
+    const bool whole_grid = a.trows == a.ntx && a.tcols == a.ntx && tiles >= 4096;
+    a.rows = (tiles > 32768 || whole_grid) ? std::min(a.T, 1024 / a.T) : std::min(a.T, 8);
     const unsigned nt = static_cast<unsigned>(tiles * (a.T / a.rows));
     if (nt == 0) return hipSuccess;
     switch (prec) {
