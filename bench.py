@@ -392,6 +392,51 @@ def interpolation_study(lmg, N, uv, vis, W=7, x0=0.25, sizes=(5, 9, 18, 36, 72, 
     return out
 
 
+def large_table_study(lmg, N, uv, vis, x0=0.25):
+    """App. F's table rates beyond LDS on the device (coefficients read from a device copy): the table's own
+    error in an FP64 dirty image of the workload, as the relative RMS distance from a reference image with a
+    negligible table error. W = 7: nearest node and linear at M_s = 1e3 .. 1e6 against direct calculation.
+    W = 14 (where direct calculation does not hold FP64 accuracy): linear at 1e3 .. 1e6 against a cubic table
+    at M_s = 1e5, whose own error is far below (error ~ M_s^-4)."""
+    import torch
+    out = {}
+    h7, _ = lmg.Table.create(7, x0, 300, 3).export()
+    ref = lmg.Plan(lmg.Table.from_h(7, x0, 300, 3, h7).direct_calculation(), N, uv, lmg.F64).make_dirty_image(vis)
+    nref = torch.linalg.vector_norm(ref).item()
+    sizes = (1000, 10000, 100000, 1000000)
+    for d in (0, 1):
+        errs = []
+        for ms in sizes:
+            t = lmg.Table.from_h(7, x0, 7 * ms, d, h7)
+            t.attach_device(lmg.F64)
+            img = lmg.Plan(t, N, uv, lmg.F64).make_dirty_image(vis)
+            errs.append(torch.linalg.vector_norm(img - ref).item() / nref)
+            del t, img
+            torch.cuda.synchronize()
+        out[f"W7_degree_{d}"] = {"Ms": list(sizes), "rel_rms_vs_direct": errs}
+        print(f"# large tables W=7 d={d}: {['%.2e' % e for e in errs]}", file=sys.stderr, flush=True)
+    del ref
+    h14, _ = lmg.Table.create(14, x0, 14 * 300, 3).export()
+    t = lmg.Table.from_h(14, x0, 14 * 100000, 3, h14)
+    t.attach_device(lmg.F64)
+    ref = lmg.Plan(t, N, uv, lmg.F64).make_dirty_image(vis)
+    nref = torch.linalg.vector_norm(ref).item()
+    del t
+    errs = []
+    for ms in sizes:
+        t = lmg.Table.from_h(14, x0, 14 * ms, 1, h14)
+        t.attach_device(lmg.F64)
+        img = lmg.Plan(t, N, uv, lmg.F64).make_dirty_image(vis)
+        errs.append(torch.linalg.vector_norm(img - ref).item() / nref)
+        del t, img
+        torch.cuda.synchronize()
+    out["W14_degree_1"] = {"Ms": list(sizes), "rel_rms_vs_cubic_1e5": errs}
+    print(f"# large tables W=14 d=1: {['%.2e' % e for e in errs]}", file=sys.stderr, flush=True)
+    out["note"] = ("FP64 dirty images of the workload; tables beyond the LDS budget read from device memory "
+                   "(lmg_table_attach_device); error = relative RMS distance from the reference image")
+    return out
+
+
 def multichannel_study(lmg, reps=5):
     """256 channels (log-uniform 1e4..2e5 visibilities), 1024^2 grids, W = 5, compensated FP32: gridding +
     degridding in one batched plan (autotuned tile) against 256 single-channel plans on one stream."""
@@ -440,6 +485,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-studies", action="store_true",
                     help="skip the precision study and the multichannel comparison")
+    ap.add_argument("--only-studies", default="", help="comma-separated study names to run (default: all)")
     ap.add_argument("--cpu-sample", type=int, default=1 << 19)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
@@ -622,7 +668,10 @@ def main():
         for key, fn in (("precision_study", lambda: precision_study(lmg, case, uv, vis.to(torch.complex64))),
                         ("direct_weights", lambda: direct_study(lmg, case, uv, vis.to(torch.complex64))),
                         ("interpolation_study", lambda: interpolation_study(lmg, case.N, uv, vis.to(torch.complex128))),
+                        ("large_table_study", lambda: large_table_study(lmg, case.N, uv, vis.to(torch.complex128))),
                         ("multichannel", lambda: multichannel_study(lmg))):
+            if args.only_studies and key not in args.only_studies.split(","):
+                continue
             try:
                 out[key] = fn()
             except Exception as e:          # a study must not cost the main line

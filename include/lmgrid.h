@@ -111,6 +111,24 @@ lmg_status lmg_table_create_from_nodes(int W, double x0, int table_size, int deg
  * conditioning then costs FP64 accuracy). */
 lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out);
 
+/* Tables larger than the kernels' LDS budget (LMG_LDS_TABLE_BYTES of
+ * coefficients: Ms above 145 at W = 7 for FP64 with cubic interpolation, 290
+ * for FP32; App. F's rates of 1e3 .. 1e6 samples per cell) are read by the
+ * kernels from device memory, through the caches, instead of being staged in
+ * LDS. Their coefficients (4 per interval and tap: float for LMG_F32 and
+ * LMG_F32_KAHAN, double for LMG_F64) live in a caller-owned device buffer
+ * attached to the table. lmg_table_device_bytes gives the buffer's size for a
+ * precision: 0 when the kernels stage the table in LDS (or for a direct
+ * table), and then nothing needs attaching. lmg_table_attach_device enqueues
+ * the copy of the coefficients into `device` on `stream` and records the
+ * buffer for that precision; plans created afterwards read it, so it must
+ * outlive them and not be written while they run. A plan whose table needs a
+ * device copy that was not attached returns LMG_ENOTSUP. Errors:
+ * LMG_EWORKSPACE (NULL or short buffer), LMG_EHIP. */
+#define LMG_LDS_TABLE_BYTES 32768
+lmg_status lmg_table_device_bytes(const lmg_table* t, lmg_precision prec, size_t* bytes);
+lmg_status lmg_table_attach_device(lmg_table* t, lmg_precision prec, void* device, size_t bytes, void* stream);
+
 /* *direct = 1 for a table made by lmg_table_create_direct, else 0. */
 lmg_status lmg_table_is_direct(const lmg_table* t, int* direct);
 

@@ -75,6 +75,8 @@ def load():
         "lmg_table_create_from_nodes": (I, [I, D, I, I, PD, PD, ctypes.POINTER(P)]),
         "lmg_table_create_direct": (I, [P, ctypes.POINTER(P)]),
         "lmg_table_is_direct": (I, [P, PI]),
+        "lmg_table_device_bytes": (I, [P, I, PZ]),
+        "lmg_table_attach_device": (I, [P, I, P, Z, P]),
         "lmg_table_info": (I, [P, PI, PD, PI, PI, PD]),
         "lmg_table_export": (I, [P, PD, PD]),
         "lmg_table_kernel": (I, [P, I, PD, PD]),
@@ -188,6 +190,26 @@ class Table:
         out = ctypes.c_void_p()
         _check(self._lib.lmg_table_create_direct(self._h, ctypes.byref(out)), "lmg_table_create_direct")
         return Table(out)
+
+    def device_bytes(self, precision: int) -> int:
+        """Bytes of the device copy the kernels read for a table too large for LDS (0 when staged in LDS)."""
+        n = ctypes.c_size_t()
+        _check(self._lib.lmg_table_device_bytes(self._h, int(precision), ctypes.byref(n)), "lmg_table_device_bytes")
+        return n.value
+
+    def attach_device(self, precision: int, device="cuda", stream=None):
+        """Copy the coefficients of a table too large for LDS into a torch-owned device buffer kept by this
+        object (lmg_table_attach_device); plans of that precision then read it. No-op when not needed."""
+        n = self.device_bytes(precision)
+        if n == 0:
+            return None
+        buf = _bytes(n, device)
+        _check(self._lib.lmg_table_attach_device(self._h, int(precision), _ptr(buf), n, _stream_handle(stream)),
+               "lmg_table_attach_device")
+        if not hasattr(self, "_device_copies"):
+            self._device_copies = {}
+        self._device_copies[2 if precision == F64 else 0] = buf
+        return buf
 
     def export(self):
         h = np.zeros(NG + 1)

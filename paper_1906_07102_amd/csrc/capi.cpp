@@ -282,9 +282,18 @@ size_t coef_bytes(const lmg_table* t, lmg_precision prec) {
     if (t->direct) return t->pq.size() * sizeof(double);
     return prec == LMG_F64 ? t->coef64.size() * sizeof(double) : t->coef32.size() * sizeof(float);
 }
-// Table intervals the kernels stage in LDS (-1: none, for a direct table) and the
-// kernels' table mode (-1: direct).
-int staged_ms(const lmg_table* t) { return t->direct ? -1 : t->Ms; }
+// A table too large for LDS: the kernels read its coefficients from the attached device copy.
+bool table_global(const lmg_table* t, lmg_precision prec) {
+    return !t->direct && coef_bytes(t, prec) > kMaxLdsTableBytes;
+}
+// Coefficient bytes a plan copies into its workspace (none for a table read from device memory).
+size_t plan_coef_bytes(const lmg_table* t, lmg_precision prec) {
+    return table_global(t, prec) ? 0 : coef_bytes(t, prec);
+}
+// Table intervals the kernels stage in LDS (-1: none, for a direct table or one read from device
+// memory), the intervals of the table, and the kernels' table mode (-1: direct).
+int staged_ms(const lmg_table* t, lmg_precision prec) { return (t->direct || table_global(t, prec)) ? -1 : t->Ms; }
+int table_ms(const lmg_table* t) { return t->direct ? -1 : t->Ms; }
 int kernel_degree(const lmg_table* t) { return t->direct ? -1 : t->degree; }
 
 // The plan constants of (table, N, precision) in pinned host memory, built on
@@ -297,7 +306,7 @@ const lmg_table::Pinned* pinned_constants(const lmg_table* t, int N, lmg_precisi
     if (it != t->pinned.end()) return it->second.host ? &it->second : nullptr;
     lmg_table::Pinned pc;
     const bool f64 = prec == LMG_F64;
-    pc.coef_bytes = coef_bytes(t, prec);
+    pc.coef_bytes = plan_coef_bytes(t, prec);
     pc.twiddle_bytes = 2 * static_cast<size_t>(N) * (f64 ? 8 : 4);
     pc.hpix_bytes = static_cast<size_t>(N) * (f64 ? 8 : 4);
     pc.coef = 0;
@@ -311,7 +320,7 @@ const lmg_table::Pinned* pinned_constants(const lmg_table* t, int N, lmg_precisi
         return nullptr;
     }
     char* b = static_cast<char*>(pc.host);
-    std::memcpy(b + pc.coef, coef_host(t, prec), pc.coef_bytes);
+    if (pc.coef_bytes) std::memcpy(b + pc.coef, coef_host(t, prec), pc.coef_bytes);
     if (f64) {
         std::memcpy(b + pc.twiddle, twiddles_f64(N).data(), pc.twiddle_bytes);
         std::memcpy(b + pc.hpix, h.data(), pc.hpix_bytes);
@@ -452,7 +461,8 @@ lmg_status run_grid_entries(const lmg_plan* p, const void* vs, void* grid, void*
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters, 1, s));
     GridArgs a{};
-    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = staged_ms(t); a.degree = kernel_degree(t);
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = table_ms(t); a.degree = kernel_degree(t);
+    a.tab_global = table_global(t, p->prec) ? 1 : 0;
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.vis = vs; a.patches = patches; a.counter = counters;
@@ -493,7 +503,8 @@ lmg_status run_degrid_entries(const lmg_plan* p, const void* grid, void* vs, int
     if (wait_plan(p, s) != LMG_OK) return LMG_EHIP;
     LMG_HIP(launch_zero_ints(counters + 1, 1, s));
     DegridArgs a{};
-    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = staged_ms(t); a.degree = kernel_degree(t);
+    a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = table_ms(t); a.degree = kernel_degree(t);
+    a.tab_global = table_global(t, p->prec) ? 1 : 0;
     a.n_items = p->flags + 1; a.max_items = p->max_items; a.F = p->F;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
@@ -548,12 +559,12 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     if (nvis < 0 || nvis > INT32_MAX || (nvis > 0 && !uv)) return LMG_EINVAL;
     if (tile != 0 && (!is_pow2(tile) || tile < 8 || tile < table->W || tile > 128 || tile > N || N / tile > 128))
         return LMG_EINVAL;
-    const size_t tab_bytes = coef_bytes(table, prec);
-    if (tab_bytes > kMaxLdsTableBytes) return LMG_ENOTSUP;
-    const int T = tile ? tile : fit_tile(choose_tile(N, table->W), N, prec, table->W, staged_ms(table));
+    const size_t tab_bytes = plan_coef_bytes(table, prec);
+    if (table_global(table, prec) && !table->dev_coef[prec == LMG_F64 ? 1 : 0]) return LMG_ENOTSUP;
+    const int T = tile ? tile : fit_tile(choose_tile(N, table->W), N, prec, table->W, staged_ms(table, prec));
     if (T < table->W || N / T > 128) return LMG_ENOTSUP;      // cannot happen for N >= 2W, N <= 8192
-    const int waves = fit_waves(T, prec, table->W, staged_ms(table));
-    if (grid_lds_bytes(prec, table->W, T, staged_ms(table), waves) > kMaxDynLds) return LMG_ENOTSUP;
+    const int waves = fit_waves(T, prec, table->W, staged_ms(table, prec));
+    if (grid_lds_bytes(prec, table->W, T, staged_ms(table, prec), waves) > kMaxDynLds) return LMG_ENOTSUP;
     const int cap = choose_cap();
     const Layout L = plan_layout(N, nvis, prec, cap, nchan);
     if (!workspace || ws_bytes < L.total) return LMG_EWORKSPACE;
@@ -590,7 +601,7 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     p->lb = 0;
     while ((1 << p->lb) < T) ++p->lb;
     p->F = packed_frac_bits(prec == LMG_F64, p->lb);
-    p->coef = base + L.coef;
+    p->coef = table_global(table, prec) ? table->dev_coef[prec == LMG_F64 ? 1 : 0] : base + L.coef;
     p->twiddle = base + L.twiddle;
     p->hpix = base + L.hpix;
 

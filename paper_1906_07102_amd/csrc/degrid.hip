@@ -19,14 +19,14 @@ namespace dev {
 // 4096^2: 256 threads 213 us, 512 191 us, 1024 189 us; 256 channels of
 // 1024^2, items of ~250 visibilities: 414, 395, 382 us).
 constexpr int kDegridThreads = 1024;
-template <typename R, int W, bool kDirect>
+template <typename R, int W, int kTab>
 __global__ __launch_bounds__(kDegridThreads) void k_degrid_items(DegridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
     using VT = typename C2<R>::T;
     using PT2 = typename Pack<R>::T2;
     R* tab = reinterpret_cast<R*>(smem);
-    const int ntab = (a.Ms + 1) * W * 4;
+    const int ntab = kTab == kTabLds ? (a.Ms + 1) * W * 4 : 0;
     VT* patch = reinterpret_cast<VT*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
     const int P = a.T + W - 1;
     const int ntiles = a.ntx * a.ntx;
@@ -55,9 +55,12 @@ __global__ __launch_bounds__(kDegridThreads) void k_degrid_items(DegridArgs a) {
             const PT2 d = off[e];
             const int cu = static_cast<int>(d.x >> cshift), cv = static_cast<int>(d.y >> cshift);
             R wu[W], wv[W];
-            if constexpr (kDirect) {
+            if constexpr (kTab == kTabDirect) {
                 weights_direct<R, W>(static_cast<const double*>(a.coef), d.x, a.F, wu);
                 weights_direct<R, W>(static_cast<const double*>(a.coef), d.y, a.F, wv);
+            } else if constexpr (kTab == kTabGlobal) {
+                weights<R, W>(gtab, a.Ms, a.degree, d.x, a.F, wu);
+                weights<R, W>(gtab, a.Ms, a.degree, d.y, a.F, wv);
             } else {
                 weights<R, W>(tab, a.Ms, a.degree, d.x, a.F, wu);
                 weights<R, W>(tab, a.Ms, a.degree, d.y, a.F, wv);
@@ -88,23 +91,26 @@ __global__ __launch_bounds__(kDegridThreads) void k_degrid_items(DegridArgs a) {
 }  // namespace dev
 
 namespace {
-template <typename R, int W, bool kDirect>
+template <typename R, int W, int kTab>
 hipError_t launch_degrid_w(const DegridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
-    const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
+    const size_t tab = kTab == kTabLds ? ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15) : 0;
     const size_t shm = tab + static_cast<size_t>(P) * P * sizeof(typename dev::C2<R>::T);
-    const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W, kDirect>);
+    const void* fn = reinterpret_cast<const void*>(&dev::k_degrid_items<R, W, kTab>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
     const int nb = std::min(a.max_items, resident_blocks(shm));
-    hipLaunchKernelGGL((dev::k_degrid_items<R, W, kDirect>), dim3(nb), dim3(dev::kDegridThreads), shm, s, a);
+    hipLaunchKernelGGL((dev::k_degrid_items<R, W, kTab>), dim3(nb), dim3(dev::kDegridThreads), shm, s, a);
     return hipGetLastError();
 }
 template <typename R>
 hipError_t dispatch_degrid(const DegridArgs& a, hipStream_t s) {
     switch (a.W) {
 #define LMG_CASE(w) \
-    case w: return a.degree < 0 ? launch_degrid_w<R, w, true>(a, s) : launch_degrid_w<R, w, false>(a, s);
+    case w:                                                                                            \
+        return a.degree < 0 ? launch_degrid_w<R, w, kTabDirect>(a, s)                                 \
+               : a.tab_global ? launch_degrid_w<R, w, kTabGlobal>(a, s)                              \
+                              : launch_degrid_w<R, w, kTabLds>(a, s);
         LMG_CASE(1) LMG_CASE(2) LMG_CASE(3) LMG_CASE(4) LMG_CASE(5) LMG_CASE(6) LMG_CASE(7) LMG_CASE(8)
         LMG_CASE(9) LMG_CASE(10) LMG_CASE(11) LMG_CASE(12) LMG_CASE(13) LMG_CASE(14) LMG_CASE(15) LMG_CASE(16)
 #undef LMG_CASE

@@ -55,25 +55,36 @@ __device__ __forceinline__ bool tap_geometry(double u, int W, double ref, int N,
 // packed offset word p (the fixed-point x = delta - delta_lo in its low F + 1
 // bits): the interval k = floor(Ms x) and t = Ms x - k are taken exactly in
 // integers; degree 0 takes the nearest node (ties to the upper one).
+// The product q Ms is 64-bit for the FP32 words (q < 2^29, Ms < 2^31) and
+// 128-bit for the FP64 words (q < 2^53), split as (hi, lo); the table pointer
+// is LDS or global memory (tables too large for LDS).
 template <typename R, int W, typename P>
 __device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int degree, P p, int F, R* out) {
     const unsigned long long q = static_cast<unsigned long long>(p) & ((2ull << F) - 1);
     const unsigned long long m = q * static_cast<unsigned long long>(Ms);
+    const unsigned long long mhi = sizeof(R) == 8 ? __umul64hi(q, static_cast<unsigned long long>(Ms)) : 0ull;
+    // floor((hi 2^64 + lo) / 2^F) for F < 64 (hi is zero whenever the true quotient is below 2^(64 - F))
+    auto shifted = [F](unsigned long long hi, unsigned long long lo) {
+        return (hi << (64 - F)) | (lo >> F);
+    };
     if (degree == 0) {
-        const int k = min(static_cast<int>((m + (1ull << (F - 1))) >> F), Ms);
-        const R* c = tab + k * W * 4;
+        const unsigned long long half = 1ull << (F - 1);
+        const unsigned long long lo = m + half;
+        const unsigned long long kk = shifted(mhi + (lo < m ? 1ull : 0ull), lo);
+        const int k = static_cast<int>(min(kk, static_cast<unsigned long long>(Ms)));
+        const R* c = tab + static_cast<size_t>(k) * W * 4;
 #pragma unroll
         for (int j = 0; j < W; ++j) out[j] = c[j * 4];
         return;
     }
-    const int k = min(static_cast<int>(m >> F), Ms);
-    const unsigned long long r = m - (static_cast<unsigned long long>(k) << F);   // < 2^F
+    const int k = static_cast<int>(min(shifted(mhi, m), static_cast<unsigned long long>(Ms)));
+    const unsigned long long r = m - (static_cast<unsigned long long>(k) << F);   // < 2^F (low bits of q Ms)
     R t;
     if constexpr (sizeof(R) == 4)
         t = static_cast<float>(static_cast<unsigned>(r)) * __int_as_float((127 - F) << 23);
     else
         t = static_cast<double>(r) * __longlong_as_double(static_cast<long long>(1023 - F) << 52);
-    const R* c = tab + k * W * 4;
+    const R* c = tab + static_cast<size_t>(k) * W * 4;
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         const R* qq = c + j * 4;

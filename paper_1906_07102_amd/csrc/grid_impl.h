@@ -208,7 +208,7 @@ __device__ __forceinline__ void flush_rows(typename Acc::Cell* patch, unsigned c
 // (a.counter, zero at launch) until none are left, so the table is staged
 // once per workgroup and uneven items (many channels of very different
 // sizes) balance dynamically.
-template <typename R, typename Acc, int W, bool kDirect>
+template <typename R, typename Acc, int W, int kTab>
 __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_item;
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
     const int P = a.T + W - 1;
     const int P2 = P * P;
     R* tab = reinterpret_cast<R*>(smem);
-    const int ntab = (a.Ms + 1) * W * 4;
+    const int ntab = kTab == kTabLds ? (a.Ms + 1) * W * 4 : 0;
     Cell* patches = reinterpret_cast<Cell*>(smem + ((ntab * sizeof(R) + 15) & ~size_t(15)));
     const int nw = a.waves;
     unsigned char* owners = reinterpret_cast<unsigned char*>(patches + nw * P2);   // a lane id per cell
@@ -265,9 +265,12 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
                     for (int u = 0; u < kB; ++u) {
                         if (j0 + u >= len) break;
                         R cu[W], cv[W];
-                        if constexpr (kDirect) {
+                        if constexpr (kTab == kTabDirect) {
                             weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].x, a.F, cu);
                             weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].y, a.F, cv);
+                        } else if constexpr (kTab == kTabGlobal) {
+                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].x, a.F, cu);
+                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].y, a.F, cv);
                         } else {
                             weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
                             weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
@@ -357,23 +360,26 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(AssembleArgs a) {
 }  // namespace dev
 
 namespace grid_impl {
-template <typename R, typename Acc, int W, bool kDirect>
+template <typename R, typename Acc, int W, int kTab>
 hipError_t launch_grid_w(const GridArgs& a, hipStream_t s) {
     const int P = a.T + W - 1;
-    const size_t tab = ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15);
+    const size_t tab = kTab == kTabLds ? ((static_cast<size_t>(a.Ms + 1) * W * 4 * sizeof(R)) + 15) & ~size_t(15) : 0;
     const size_t shm = tab + static_cast<size_t>(P) * P * (sizeof(typename Acc::Cell) + 1) * a.waves;
-    const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W, kDirect>);
+    const void* fn = reinterpret_cast<const void*>(&dev::k_grid_items<R, Acc, W, kTab>);
     static const hipError_t attr = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynLds);
     if (attr != hipSuccess) return attr;
     const int nb = std::min(a.max_items, resident_blocks(shm));
-    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W, kDirect>), dim3(nb), dim3(64 * a.waves), shm, s, a);
+    hipLaunchKernelGGL((dev::k_grid_items<R, Acc, W, kTab>), dim3(nb), dim3(64 * a.waves), shm, s, a);
     return hipGetLastError();
 }
 template <typename R, typename Acc>
 hipError_t dispatch_grid(const GridArgs& a, hipStream_t s) {
     switch (a.W) {
 #define LMG_CASE(w) \
-    case w: return a.degree < 0 ? launch_grid_w<R, Acc, w, true>(a, s) : launch_grid_w<R, Acc, w, false>(a, s);
+    case w:                                                                                            \
+        return a.degree < 0 ? launch_grid_w<R, Acc, w, kTabDirect>(a, s)                              \
+               : a.tab_global ? launch_grid_w<R, Acc, w, kTabGlobal>(a, s)                           \
+                              : launch_grid_w<R, Acc, w, kTabLds>(a, s);
         LMG_CASE(1) LMG_CASE(2) LMG_CASE(3) LMG_CASE(4) LMG_CASE(5) LMG_CASE(6) LMG_CASE(7) LMG_CASE(8)
         LMG_CASE(9) LMG_CASE(10) LMG_CASE(11) LMG_CASE(12) LMG_CASE(13) LMG_CASE(14) LMG_CASE(15) LMG_CASE(16)
 #undef LMG_CASE

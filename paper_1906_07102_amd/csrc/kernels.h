@@ -32,11 +32,17 @@ struct PlanGeom {
     double ref;   // offset of the reference tap from the first tap
 };
 
-// Ms: table intervals staged in LDS; degree: interpolation degree. A direct
-// table has Ms = -1 (nothing staged) and degree = -1, and coef holds its FP64
-// expansion (the weights are computed per visibility).
+// How the kernels get the tap weights: from the coefficient table staged in
+// LDS, evaluated directly per visibility (the table's FP64 expansion), or
+// from a coefficient table read through the caches (too large for LDS).
+constexpr int kTabLds = 0, kTabDirect = 1, kTabGlobal = 2;
+
+// Ms: table intervals (staged in LDS unless tab_global); degree: interpolation
+// degree. A direct table has Ms = -1 (nothing staged) and degree = -1, and coef
+// holds its FP64 expansion (the weights are computed per visibility).
 struct GridArgs {
     int N, W, T, ntx, Ms, degree;
+    int tab_global;        // 1: read the coefficient table from device memory, not LDS
     const int* n_items;    // device: number of work items (written by the plan)
     int max_items;         // most work items the plan can have (sizes the launch)
     int waves;             // waves per workgroup, 1..4, each with its own LDS patch
@@ -62,6 +68,7 @@ struct AssembleArgs {
 
 struct DegridArgs {
     int N, W, T, ntx, Ms, degree;
+    int tab_global;        // 1: read the coefficient table from device memory, not LDS
     const int* n_items;
     int max_items;
     int F;

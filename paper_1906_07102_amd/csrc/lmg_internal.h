@@ -39,6 +39,10 @@ struct lmg_table {
     // 2 pi delta x0 / kNg; FP64 in every precision mode.
     bool direct = false;
     std::vector<double> pq;
+    // Device copies of the coefficients (caller-owned buffers, lmg_table_attach_device) for tables too
+    // large for LDS: [0] float coefficients (FP32 modes), [1] double (FP64).
+    void* dev_coef[2] = {nullptr, nullptr};
+    size_t dev_bytes[2] = {0, 0};
     // Correction vectors already computed, by grid size.
     mutable std::mutex cache_mu;
     mutable std::map<int, std::vector<double>> hpix_cache;

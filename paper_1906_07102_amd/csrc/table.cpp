@@ -601,6 +601,29 @@ lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out) {
     return LMG_OK;
 }
 
+lmg_status lmg_table_device_bytes(const lmg_table* t, lmg_precision prec, size_t* bytes) {
+    if (!t || !bytes || prec < LMG_F32 || prec > LMG_F64) return LMG_EINVAL;
+    const size_t b = prec == LMG_F64 ? t->coef64.size() * sizeof(double) : t->coef32.size() * sizeof(float);
+    *bytes = (t->direct || b <= kMaxLdsTableBytes) ? 0 : b;
+    return LMG_OK;
+}
+
+lmg_status lmg_table_attach_device(lmg_table* t, lmg_precision prec, void* device, size_t bytes, void* stream) {
+    size_t need = 0;
+    const lmg_status st = lmg_table_device_bytes(t, prec, &need);
+    if (st != LMG_OK) return st;
+    if (need == 0) return LMG_OK;                      // the kernels stage this table in LDS
+    if (!device || bytes < need) return LMG_EWORKSPACE;
+    const int i = prec == LMG_F64 ? 1 : 0;
+    const void* src = i ? static_cast<const void*>(t->coef64.data()) : static_cast<const void*>(t->coef32.data());
+    if (hipMemcpyAsync(device, src, need, hipMemcpyHostToDevice, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return LMG_EHIP;
+    // (pageable host memory: the copy has left the host buffer when hipMemcpyAsync returns)
+    t->dev_coef[i] = device;
+    t->dev_bytes[i] = need;
+    return LMG_OK;
+}
+
 lmg_status lmg_table_is_direct(const lmg_table* t, int* direct) {
     if (!t || !direct) return LMG_EINVAL;
     *direct = t->direct ? 1 : 0;
