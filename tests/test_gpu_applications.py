@@ -79,3 +79,25 @@ def test_major_cycle_with_the_true_model(prec):
           flush=True)
     assert rv < (1e-6 if prec == lmg.F64 else 2e-5)
     assert ri < (1e-6 if prec == lmg.F64 else 2e-5)
+
+
+@pytest.mark.parametrize("prec", [lmg.F64, lmg.F32])
+def test_spheroidal_table_through_the_library(prec):
+    """A table of the comparison system (the alpha = 1 spheroidal function, oracle-side) taken as data by
+    lmg_table_create_from_nodes: the kernels grid and degrid with it as with any table (the correction is
+    not involved)."""
+    from oracle import spheroidal as sp
+    stab = sp.table(7, 42, 3)
+    gtab = lmg.Table.from_nodes(7, 0.25, 300, 3, np.ones(33), stab.nodes)
+    c = synth.small_case()
+    cdt = torch.complex128 if prec == lmg.F64 else torch.complex64
+    plan = lmg.Plan(gtab, c.N, torch.as_tensor(c.uv, device=DEV), prec)
+    g = plan.grid(torch.as_tensor(c.vis, device=DEV).to(cdt)).cpu().numpy()
+    ref = im.grid(c.uv, c.vis, None, c.N, stab)
+    tol = 1e-12 if prec == lmg.F64 else 1e-5
+    assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < tol
+    rng = np.random.default_rng(43)
+    G = rng.standard_normal((c.N, c.N)) + 1j * rng.standard_normal((c.N, c.N))
+    out = plan.degrid(torch.as_tensor(G, device=DEV).to(cdt)).cpu().numpy()
+    ref_v = im.degrid(c.uv, G, stab)
+    assert np.linalg.norm(out - ref_v) / np.linalg.norm(ref_v) < tol
