@@ -253,14 +253,25 @@ def cpu_baseline(case, nvis_sample: int):
     t4 = time.perf_counter()
     per_vis = ((t1 - t0) + (t4 - t3)) / nvis_sample
     step = per_vis * len(case.uv) + (t2 - t1) + (t3 - t2)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": len(case.uv) / step,
         "unit": "visibilities/s",
         "cores": 1,
+        "cpu_model": model,
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"FP64 NumPy oracle: grid + degrid of the first {nvis_sample} visibilities "
                    f"({(t1 - t0) + (t4 - t3):.1f} s) and one inverse + one forward {case.N}^2 radix-2 FFT with "
-                   f"correction ({(t2 - t1) + (t3 - t2):.1f} s), scaled to the full {len(case.uv)}-visibility step"),
+                   f"correction ({(t2 - t1) + (t3 - t2):.1f} s), scaled to the full {len(case.uv)}-visibility step; "
+                   f"NumPy on one thread"),
         "seconds": round(t4 - t0, 2),
     }
 
@@ -437,6 +448,123 @@ def large_table_study(lmg, N, uv, vis, x0=0.25):
     return out
 
 
+def _dirty_from_grid(lmg, G, hpix, M):
+    """Centred inverse FFT of one grid (library FFT), correction h(x) h(y) and crop to M x M (torch glue)."""
+    import torch
+    N = G.shape[0]
+    F = lmg.fft2_centred(G.clone(), +1)
+    sl = slice(N // 2 - M // 2, N // 2 + M // 2)
+    h = torch.as_tensor(hpix[sl], device=G.device, dtype=torch.float64)
+    return F[sl, sl].to(torch.complex128) * h[:, None] * h[None, :]
+
+
+def north_star_comparison(lmg, case, uv16, vis16, reps=3):
+    """The batched, differentiable, compensated-FP32 form against the plain one-channel FP64 path, at equal
+    misfit against the direct DFT.
+
+    W = 5, 256 channels (1024^2, log-uniform counts): one batched compensated-FP32 plan through autograd
+    (forward = degridding of 256 model grids, loss = sum |V_hat - V|^2, backward = gridding) against 256
+    single-channel FP64 plans doing the same degrid + grid of the residual. At W = 5 both reach the method's
+    own misfit (FP32 rounding is far below it), measured on four channels' dirty images against the direct-DFT
+    samples of tests/golden/dft_multichannel.npz.
+    W = 7, 16.8M visibilities on 4096^2 (the paper's single-precision level): prediction through autograd
+    (forward = predict_visibilities of the image, backward = dirty image) in compensated FP32 against the same
+    forward and backward in FP64. FP64 needs W = 7 to stay at or below the compensated form's misfit, so the
+    pair is W = 7 against W = 7 (FP64 then has the smaller misfit: the comparison favours FP64)."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    out = {}
+    # ---- W = 5, batched
+    uv_np, off, _ = synth.multichannel_case()
+    uv = torch.from_numpy(uv_np).to(dev)
+    v32 = torch.from_numpy(synth.multichannel_vis(len(uv_np))).to(dev)
+    v64 = v32.to(torch.complex128)
+    N, W, M = 1024, 5, 512
+    nch = len(off) - 1
+    table = lmg.Table.create(W, 0.25, 300, 3)
+    bplan = lmg.BatchPlan(table, N, uv, off, lmg.F32_KAHAN, tile=32)
+    singles = [lmg.Plan(table, N, uv[int(off[c]):int(off[c + 1])].contiguous(), lmg.F64) for c in range(nch)]
+    G32 = bplan.grid(v32)
+    G64 = G32.to(torch.complex128)
+    grad64 = torch.empty_like(G64)
+
+    def batched():
+        g = G32.detach().requires_grad_(True)
+        vh = lmg.Degrid.apply(bplan, g)
+        (vh - v32).abs().pow(2).sum().backward()
+        return g.grad
+
+    def fp64_separate():
+        for c, p in enumerate(singles):
+            a, b = int(off[c]), int(off[c + 1])
+            vh = p.degrid(G64[c])
+            p.grid(2 * (vh - v64[a:b]), out=grad64[c])
+
+    ms_b = _timed(batched, reps)
+    ms_s = _timed(fp64_separate, max(1, reps // 2))
+    gold = np.load(os.path.join(HERE, "tests", "golden", "dft_multichannel.npz"))
+    hpix = table.correction(N)
+    sel = torch.as_tensor(-256 + 8 * np.arange(64) + M // 2, device=dev)
+    mis_k, mis_64 = [], []
+    for c in (0, 85, 170, 255):
+        a, b = int(off[c]), int(off[c + 1])
+        ref = gold[f"chan_{c}"]
+        ik = _dirty_from_grid(lmg, G32[c], hpix, M)
+        i64 = singles[c].make_dirty_image(v64[a:b])
+        for img, dst in ((ik, mis_k), (i64, mis_64)):
+            smp = img.index_select(0, sel).index_select(1, sel).to(torch.complex128).cpu().numpy()
+            dst.append(float(np.linalg.norm(smp - ref) / np.linalg.norm(ref)))
+    out["W5_batched_256_channels"] = {
+        "nvis": int(off[-1]), "ms_batched_differentiable_kahan": round(ms_b, 4),
+        "ms_256_single_channel_fp64": round(ms_s, 4), "speedup": round(ms_s / ms_b, 2),
+        "dft_misfit_kahan_channels_0_85_170_255": mis_k, "dft_misfit_fp64_channels_0_85_170_255": mis_64,
+    }
+    print(f"# north star W=5: batched kahan {ms_b:.2f} ms, 256 x fp64 {ms_s:.2f} ms; misfit {mis_k} vs {mis_64}",
+          file=sys.stderr, flush=True)
+    del bplan, singles, G32, G64, grad64
+    torch.cuda.synchronize()
+    # ---- W = 7, one channel of 16.8M visibilities
+    t7 = lmg.Table.create(7, case.x0, case.table_size, case.degree)
+    pk = lmg.Plan(t7, case.N, uv16, lmg.F32_KAHAN)
+    p64 = lmg.Plan(t7, case.N, uv16, lmg.F64)
+    v7 = vis16.to(torch.complex64)
+    v7d = vis16.to(torch.complex128)
+    img_k = pk.make_dirty_image(v7)
+    img_64 = p64.make_dirty_image(v7d)
+    model_k = img_k / float(len(case.uv))
+    model_64 = model_k.to(torch.complex128)
+
+    def diff_kahan():
+        im_ = model_k.detach().requires_grad_(True)
+        vh = lmg.PredictVisibilities.apply(pk, im_)
+        (vh - v7).abs().pow(2).sum().backward()
+        return im_.grad
+
+    def fp64_plain():
+        vh = p64.predict_visibilities(model_64)
+        return p64.make_dirty_image(2 * (vh - v7d))
+
+    ms_k7 = _timed(diff_kahan, reps)
+    ms_64 = _timed(fp64_plain, reps)
+    dft = np.load(os.path.join(HERE, "tests", "golden", "dft_samples_16m_4096.npy"))
+    sel = torch.as_tensor(-1024 + 8 * np.arange(256) + pk.M // 2, device=dev)
+    mis = []
+    for img in (img_k, img_64):
+        smp = img.index_select(0, sel).index_select(1, sel).to(torch.complex128).cpu().numpy()
+        mis.append(float(np.linalg.norm(smp - dft) / np.linalg.norm(dft)))
+    out["W7_single_precision_level"] = {
+        "nvis": len(case.uv), "ms_differentiable_kahan": round(ms_k7, 4), "ms_fp64": round(ms_64, 4),
+        "speedup": round(ms_64 / ms_k7, 3), "dft_misfit_kahan": mis[0], "dft_misfit_fp64": mis[1],
+    }
+    print(f"# north star W=7: kahan {ms_k7:.3f} ms, fp64 {ms_64:.3f} ms; misfit {mis}", file=sys.stderr,
+          flush=True)
+    out["pairing"] = ("W = 5: both forms reach the method's own misfit (equal to 3 digits on four channels); "
+                      "W = 7: FP64 needs the same W to stay at or below the compensated form's misfit, and "
+                      "then has the smaller misfit (the comparison favours FP64)")
+    return out
+
+
 def multichannel_study(lmg, reps=5):
     """256 channels (log-uniform 1e4..2e5 visibilities), 1024^2 grids, W = 5, compensated FP32: gridding +
     degridding in one batched plan (autotuned tile) against 256 single-channel plans on one stream."""
@@ -444,9 +572,7 @@ def multichannel_study(lmg, reps=5):
     import synth
     uv_np, off, _ = synth.multichannel_case()
     dev = torch.device("cuda:0")
-    rng = np.random.default_rng(55)
-    vis = torch.from_numpy((rng.standard_normal(len(uv_np)) + 1j * rng.standard_normal(len(uv_np)))
-                           .astype(np.complex64)).to(dev)
+    vis = torch.from_numpy(synth.multichannel_vis(len(uv_np))).to(dev)
     uv = torch.from_numpy(uv_np).to(dev)
     N, W = 1024, 5
     table = lmg.Table.create(W, 0.25, 300, 3)
@@ -669,7 +795,8 @@ def main():
                         ("direct_weights", lambda: direct_study(lmg, case, uv, vis.to(torch.complex64))),
                         ("interpolation_study", lambda: interpolation_study(lmg, case.N, uv, vis.to(torch.complex128))),
                         ("large_table_study", lambda: large_table_study(lmg, case.N, uv, vis.to(torch.complex128))),
-                        ("multichannel", lambda: multichannel_study(lmg))):
+                        ("multichannel", lambda: multichannel_study(lmg)),
+                        ("north_star_comparison", lambda: north_star_comparison(lmg, case, uv, vis))):
             if args.only_studies and key not in args.only_studies.split(","):
                 continue
             try:

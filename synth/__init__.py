@@ -162,3 +162,9 @@ def multichannel_case(seed: int = 5, nchan: int = 256, N: int = 1024, W: int = 5
     scale = cell_scale(allv, N, W)        # the largest |u|, |v| come from the shortest wavelength
     offsets = np.concatenate([[0], np.cumsum(counts)])
     return allv * scale, offsets, lams
+
+
+def multichannel_vis(n: int, seed: int = 55) -> np.ndarray:
+    """Complex N(0, 1) visibilities for the multi-channel case, rounded to complex64."""
+    rng = np.random.default_rng(seed)
+    return (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64)
