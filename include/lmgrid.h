@@ -123,7 +123,8 @@ lmg_status lmg_table_create_direct(const lmg_table* from, lmg_table** out);
  * the copy of the coefficients into `device` on `stream` and records the
  * buffer for that precision; plans created afterwards read it, so it must
  * outlive them and not be written while they run. A plan whose table needs a
- * device copy that was not attached returns LMG_ENOTSUP. Errors:
+ * device copy that was not attached returns LMG_ENOTSUP, and so does a plan
+ * for a table of 2^24 or more intervals (Ms >= 16,777,216). Errors:
  * LMG_EWORKSPACE (NULL or short buffer), LMG_EHIP. */
 #define LMG_LDS_TABLE_BYTES 32768
 lmg_status lmg_table_device_bytes(const lmg_table* t, lmg_precision prec, size_t* bytes);

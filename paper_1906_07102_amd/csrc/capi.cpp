@@ -61,7 +61,9 @@ struct lmg_plan {
     int* inv = nullptr;            // caller index -> entry (-1: dropped)
     int2* pieces = nullptr;
     int lb = 0;                    // log2 of the tile edge
-    int F = 0;                     // fraction bits of the packed offsets
+    int ms_enc = 1;                // packed offsets: table intervals they are packed for (1: direct table)
+    int kb = 1;                    // packed offsets: bits of the interval index (bits of ms_enc)
+    int Ft = 0;                    // packed offsets: bits of the in-interval fraction
     void* coef = nullptr;
     void* twiddle = nullptr;
     void* hpix = nullptr;
@@ -463,7 +465,7 @@ lmg_status run_grid_entries(const lmg_plan* p, const void* vs, void* grid, void*
     GridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = table_ms(t); a.degree = kernel_degree(t);
     a.tab_global = table_global(t, p->prec) ? 1 : 0;
-    a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.F = p->F;
+    a.n_items = p->flags + 1; a.max_items = p->max_items; a.waves = p->waves; a.Ft = p->Ft; a.kb = p->kb;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.vis = vs; a.patches = patches; a.counter = counters;
     {
@@ -505,7 +507,7 @@ lmg_status run_degrid_entries(const lmg_plan* p, const void* grid, void* vs, int
     DegridArgs a{};
     a.N = p->g.N; a.W = p->g.W; a.T = p->g.T; a.ntx = p->g.ntx; a.Ms = table_ms(t); a.degree = kernel_degree(t);
     a.tab_global = table_global(t, p->prec) ? 1 : 0;
-    a.n_items = p->flags + 1; a.max_items = p->max_items; a.F = p->F;
+    a.n_items = p->flags + 1; a.max_items = p->max_items; a.Ft = p->Ft; a.kb = p->kb;
     a.items = p->items; a.pieces = p->pieces; a.off = p->off; a.coef = p->coef;
     a.grid = grid; a.vis_out = vs; a.counter = counters + 1;
     TraceScope ts("degrid_items", s);
@@ -600,7 +602,12 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
     p->pieces = reinterpret_cast<int2*>(base + L.pieces);
     p->lb = 0;
     while ((1 << p->lb) < T) ++p->lb;
-    p->F = packed_frac_bits(prec == LMG_F64, p->lb);
+    // Packed offsets hold the interval index in kb <= 24 bits over Ft >= 2 fraction bits.
+    p->ms_enc = table->direct ? 1 : table->Ms;
+    p->kb = 0;
+    while (p->kb < 31 && (p->ms_enc >> p->kb) != 0) ++p->kb;
+    p->Ft = packed_cell_shift(prec == LMG_F64, p->lb) - p->kb;
+    if (p->kb > 24 || p->Ft < 2) return LMG_ENOTSUP;
     p->coef = table_global(table, prec) ? table->dev_coef[prec == LMG_F64 ? 1 : 0] : base + L.coef;
     p->twiddle = base + L.twiddle;
     p->hpix = base + L.hpix;
@@ -672,7 +679,7 @@ lmg_status create_plan(const lmg_table* table, int N, lmg_precision prec, int nc
         TraceScope ts("plan_scatter", s);
         // packed offsets by caller index go to `off` for now (the item sort overwrites it)
         LMG_HIP(launch_plan_scatter(prec == LMG_F64, uv, p->blocks, p->nblocks, p->g, p->tile_start, p->blockhist,
-                                    delta_low(table->W), p->lb, p->inv0, p->off, s));
+                                    delta_low(table->W), p->lb, p->ms_enc, p->kb, p->inv0, p->off, s));
     }
     {
         TraceScope ts("plan_place", s);

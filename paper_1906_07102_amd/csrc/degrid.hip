@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kDegridThreads) void k_degrid_items(DegridArgs a) {
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) tab[i] = gtab[i];
     VT* out = reinterpret_cast<VT*>(a.vis_out);     // entry order
     const PT2* off = reinterpret_cast<const PT2*>(a.off);
-    const int cshift = a.F + 1;
+    const int cshift = a.Ft + a.kb;
     const int nitems = *a.n_items;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
@@ -56,14 +56,14 @@ __global__ __launch_bounds__(kDegridThreads) void k_degrid_items(DegridArgs a) {
             const int cu = static_cast<int>(d.x >> cshift), cv = static_cast<int>(d.y >> cshift);
             R wu[W], wv[W];
             if constexpr (kTab == kTabDirect) {
-                weights_direct<R, W>(static_cast<const double*>(a.coef), d.x, a.F, wu);
-                weights_direct<R, W>(static_cast<const double*>(a.coef), d.y, a.F, wv);
+                weights_direct<R, W>(static_cast<const double*>(a.coef), d.x, a.Ft, wu);
+                weights_direct<R, W>(static_cast<const double*>(a.coef), d.y, a.Ft, wv);
             } else if constexpr (kTab == kTabGlobal) {
-                weights<R, W>(gtab, a.Ms, a.degree, d.x, a.F, wu);
-                weights<R, W>(gtab, a.Ms, a.degree, d.y, a.F, wv);
+                weights<R, W>(gtab, a.Ms, a.degree, d.x, a.Ft, a.kb, wu);
+                weights<R, W>(gtab, a.Ms, a.degree, d.y, a.Ft, a.kb, wv);
             } else {
-                weights<R, W>(tab, a.Ms, a.degree, d.x, a.F, wu);
-                weights<R, W>(tab, a.Ms, a.degree, d.y, a.F, wv);
+                weights<R, W>(tab, a.Ms, a.degree, d.x, a.Ft, a.kb, wu);
+                weights<R, W>(tab, a.Ms, a.degree, d.y, a.Ft, a.kb, wv);
             }
             const VT* row = patch + cv * P + cu;
             R accr = 0, acci = 0;

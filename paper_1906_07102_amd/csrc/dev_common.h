@@ -51,40 +51,31 @@ __device__ __forceinline__ bool tap_geometry(double u, int W, double ref, int N,
     return true;
 }
 
-// W kernel weights from the coefficient table in LDS (App. F) for the
-// packed offset word p (the fixed-point x = delta - delta_lo in its low F + 1
-// bits): the interval k = floor(Ms x) and t = Ms x - k are taken exactly in
-// integers; degree 0 takes the nearest node (ties to the upper one).
-// The product q Ms is 64-bit for the FP32 words (q < 2^29, Ms < 2^31) and
-// 128-bit for the FP64 words (q < 2^53), split as (hi, lo); the table pointer
-// is LDS or global memory (tables too large for LDS).
+// W kernel weights from the coefficient table (App. F) for the packed
+// offset word p, which holds the interval k (kb bits) and the fixed-point
+// position t in it (Ft bits) of s = Ms x; degree 0 takes the nearest node
+// (ties to the upper one). The table pointer is LDS or global memory (tables
+// too large for LDS). k never exceeds Ms in a word the plan wrote; the clamp
+// keeps the table read in bounds for any word. Ms < 2^24 (the plan's bound),
+// so the row offset is a 24-bit product.
 template <typename R, int W, typename P>
-__device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int degree, P p, int F, R* out) {
-    const unsigned long long q = static_cast<unsigned long long>(p) & ((2ull << F) - 1);
-    const unsigned long long m = q * static_cast<unsigned long long>(Ms);
-    const unsigned long long mhi = sizeof(R) == 8 ? __umul64hi(q, static_cast<unsigned long long>(Ms)) : 0ull;
-    // floor((hi 2^64 + lo) / 2^F) for F < 64 (hi is zero whenever the true quotient is below 2^(64 - F))
-    auto shifted = [F](unsigned long long hi, unsigned long long lo) {
-        return (hi << (64 - F)) | (lo >> F);
-    };
+__device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int degree, P p, int Ft, int kb, R* out) {
+    const unsigned kq = static_cast<unsigned>(p >> Ft) & ((1u << kb) - 1);
+    const P tq = p & ((P(1) << Ft) - 1);
     if (degree == 0) {
-        const unsigned long long half = 1ull << (F - 1);
-        const unsigned long long lo = m + half;
-        const unsigned long long kk = shifted(mhi + (lo < m ? 1ull : 0ull), lo);
-        const int k = static_cast<int>(min(kk, static_cast<unsigned long long>(Ms)));
-        const R* c = tab + static_cast<size_t>(k) * W * 4;
+        const unsigned up = static_cast<unsigned>(tq >> (Ft - 1));        // t >= 1/2
+        const R* c = tab + __umul24(min(kq + up, static_cast<unsigned>(Ms)), W * 4);
 #pragma unroll
         for (int j = 0; j < W; ++j) out[j] = c[j * 4];
         return;
     }
-    const int k = static_cast<int>(min(shifted(mhi, m), static_cast<unsigned long long>(Ms)));
-    const unsigned long long r = m - (static_cast<unsigned long long>(k) << F);   // < 2^F (low bits of q Ms)
+    const unsigned k = min(kq, static_cast<unsigned>(Ms));
     R t;
     if constexpr (sizeof(R) == 4)
-        t = static_cast<float>(static_cast<unsigned>(r)) * __int_as_float((127 - F) << 23);
+        t = static_cast<float>(static_cast<unsigned>(tq)) * __int_as_float((127 - Ft) << 23);
     else
-        t = static_cast<double>(r) * __longlong_as_double(static_cast<long long>(1023 - F) << 52);
-    const R* c = tab + static_cast<size_t>(k) * W * 4;
+        t = static_cast<double>(tq) * __longlong_as_double(static_cast<long long>(1023 - Ft) << 52);
+    const R* c = tab + __umul24(k, W * 4);
 #pragma unroll
     for (int j = 0; j < W; ++j) {
         const R* qq = c + j * 4;
@@ -97,8 +88,9 @@ __device__ __forceinline__ void weights(const R* __restrict__ tab, int Ms, int d
 // C(t_j - delta) = [A^{-1} B(delta)]_j (Eq. 18), expanded on the host over the
 // 33 h samples as c_j = sum_i P_ji cos(i theta) + Q_ji sin(i theta) with
 // theta = 2 pi delta x0 / 32. pq holds P (W x 33), Q (W x 33), then 2 pi x0 /
-// 32. The offset comes back exactly from the packed word (q 2^-F above the
-// interval's low end); cos(i theta), sin(i theta) follow by the angle-sum
+// 32. The offset comes back exactly from the packed word (a direct plan packs
+// with Ms = 1: the low F + 1 bits are x 2^F, x = delta - delta_lo in [0, 1],
+// F the word's fraction bits); cos(i theta), sin(i theta) follow by the angle-sum
 // recurrence from one sincos. FP64 throughout; the coefficient index is
 // uniform across the wave, so its loads are scalar.
 template <typename R, int W, typename P>
@@ -143,11 +135,16 @@ __device__ __forceinline__ int xcd_chunk(int b, int nb) {
 // ---------------------------------------------------------------- plan
 // Packed offsets. A visibility's position in its tile and its fractional
 // offsets are kept, per axis, in one unsigned word (32-bit for the FP32
-// modes, 64-bit for FP64): the first-tap cell within the tile in the top
-// log2(T) bits, and x = delta - delta_lo in [0, 1] as the fixed-point
-// integer q = round(x 2^F) below them. With T = 32 the FP32-mode word keeps
-// x to 2^-26, finer than a float offset near |delta| = 1/2; the FP64 word
-// keeps it to 2^-52.
+// modes, 64-bit for FP64): the first-tap cell within the tile in the bits
+// from S = 32 - log2(T) (FP32 words) or S = 53 (FP64 words) up, and below
+// them the table coordinate s = Ms x of x = delta - delta_lo in [0, 1],
+// split as the interval k = floor(s) in kb bits (kb = bits of Ms) over the
+// fraction t = s - k as the Ft = S - kb bit fixed-point integer
+// round(t 2^Ft), so that the kernels take k and t with a field extract and
+// one conversion. The word keeps x to 2^-Ft / Ms <= 2^-(S-1): with T = 32,
+// 2^-26 in an FP32-mode word (finer than a float offset near |delta| = 1/2),
+// 2^-52 in an FP64 word. A direct table packs with Ms = 1 (k = 1 only at
+// x = 1), which leaves x 2^(S-1) in the low S bits.
 template <typename R> struct Pack;
 template <> struct Pack<float> {
     using T = unsigned int;
@@ -159,19 +156,29 @@ template <> struct Pack<double> {
     using T2 = ulonglong2;
     static constexpr int kBits = 64;
 };
-// Fraction bits F for tile edge T = 2^lb.
+// Position S of the cell bits for tile edge T = 2^lb.
 template <typename R>
-__host__ __device__ __forceinline__ int pack_frac_bits(int lb) {
-    return Pack<R>::kBits == 32 ? 31 - lb : 52;
+__host__ __device__ __forceinline__ int pack_cell_shift(int lb) {
+    return Pack<R>::kBits == 32 ? 32 - lb : 53;
 }
 
+// s = Ms x in FP64 (x <= 1, so s <= Ms), k = floor(s), t = s - k exactly;
+// a fraction that rounds to 1 carries into k (still at most Ms).
 template <typename R>
-__device__ __forceinline__ typename Pack<R>::T pack_axis(int local_cell, double delta, double dlo, int lb) {
+__device__ __forceinline__ typename Pack<R>::T pack_axis(int local_cell, double delta, double dlo, int lb, int ms,
+                                                        int kb) {
     using P = typename Pack<R>::T;
-    const int F = pack_frac_bits<R>(lb);
+    const int S = pack_cell_shift<R>(lb), Ft = S - kb;
     const double x = fmin(fmax(delta - dlo, 0.0), 1.0);
-    const P q = static_cast<P>(rint(x * static_cast<double>(1ull << F)));
-    return (static_cast<P>(local_cell) << (F + 1)) | q;
+    const double s = x * static_cast<double>(ms);
+    const double kf = floor(s);
+    P k = static_cast<P>(kf);
+    P tq = static_cast<P>(rint((s - kf) * static_cast<double>(1ull << Ft)));
+    if (tq >> Ft) {
+        ++k;
+        tq = 0;
+    }
+    return (static_cast<P>(local_cell) << S) | (k << Ft) | tq;
 }
 
 // Wavefront-wide inclusive sum (64 lanes).

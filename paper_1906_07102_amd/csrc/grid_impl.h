@@ -266,14 +266,14 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
                         if (j0 + u >= len) break;
                         R cu[W], cv[W];
                         if constexpr (kTab == kTabDirect) {
-                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].x, a.F, cu);
-                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].y, a.F, cv);
+                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].x, a.Ft, cu);
+                            weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].y, a.Ft, cv);
                         } else if constexpr (kTab == kTabGlobal) {
-                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].x, a.F, cu);
-                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].y, a.F, cv);
+                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].x, a.Ft, a.kb, cu);
+                            weights<R, W>(gtab, a.Ms, a.degree, dv[u].y, a.Ft, a.kb, cv);
                         } else {
-                            weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.F, cu);
-                            weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.F, cv);
+                            weights<R, W>(tab, a.Ms, a.degree, dv[u].x, a.Ft, a.kb, cu);
+                            weights<R, W>(tab, a.Ms, a.degree, dv[u].y, a.Ft, a.kb, cv);
                         }
 #pragma unroll
                         for (int r = 0; r < RG; ++r) {

@@ -46,7 +46,7 @@ struct GridArgs {
     const int* n_items;    // device: number of work items (written by the plan)
     int max_items;         // most work items the plan can have (sizes the launch)
     int waves;             // waves per workgroup, 1..4, each with its own LDS patch
-    int F;                 // fraction bits of the packed offsets
+    int Ft, kb;            // packed offsets: bits of the in-interval fraction t and of the interval k
     const int4* items;     // (tile, first position, count, pieces)
     const int2* pieces;    // (first entry, length | cell << 16)
     const void* off;       // packed offsets (uint2 or ulonglong2), entry order
@@ -71,7 +71,7 @@ struct DegridArgs {
     int tab_global;        // 1: read the coefficient table from device memory, not LDS
     const int* n_items;
     int max_items;
-    int F;
+    int Ft, kb;            // packed offsets: bits of the in-interval fraction t and of the interval k
     const int4* items;
     const int2* pieces;
     const void* off;
@@ -104,10 +104,11 @@ hipError_t launch_plan_colscan(const PlanGeom& g, int* blockhist, const int* cha
                                hipStream_t s);
 hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_start, int* item_start, int4* items,
                             int* flags, int cap, hipStream_t s);
-// inv0[k] = tile-order position, offk[k] = packed offsets (both by caller index).
+// inv0[k] = tile-order position, offk[k] = packed offsets (both by caller index), packed for a table of
+// ms intervals (1 for a direct table), kb = bits of ms.
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* offk,
-                               hipStream_t s);
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int ms, int kb,
+                               int* inv0, void* offk, hipStream_t s);
 // off0[inv0[k]] = offk[k] for the valid visibilities (flags[2] of them).
 hipError_t launch_plan_place(bool f64, const int* inv0, const void* offk, const int* flags, int64_t nvis, void* off0,
                              hipStream_t s);
@@ -116,7 +117,8 @@ hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_it
 hipError_t launch_plan_compose(const int* inv0, const int* pos2, int64_t nvis, int* inv, hipStream_t s);
 // Bytes of one visibility's packed offsets (both axes).
 size_t packed_offset_bytes(bool f64);
-int packed_frac_bits(bool f64, int lb);
+// Position of the cell bits in a packed offset word for tile edge 2^lb.
+int packed_cell_shift(bool f64, int lb);
 hipError_t launch_permute_in(bool f64, const void* vis, const float* w, const int* inv, int64_t nvis, void* vs,
                              hipStream_t s);
 hipError_t launch_zero_ints(int* p, int n, hipStream_t s);

@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
                                                                const int4* __restrict__ blocks, int nb, PlanGeom g,
                                                                const int* __restrict__ tile_start,
                                                                const int* __restrict__ blockhist, double dlo, int lb,
-                                                               int* __restrict__ inv0,
+                                                               int ms, int kb, int* __restrict__ inv0,
                                                                typename Pack<R>::T2* __restrict__ offk) {
     extern __shared__ int cur[];
     const int hs = g.ntiles + 1;
@@ -303,8 +303,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
             if (tap_geometry(c[u].x, g.W, g.ref, g.N, &cu, &du) && tap_geometry(c[u].y, g.W, g.ref, g.N, &cv, &dv)) {
                 key[u] = (cv / g.T) * g.ntx + (cu / g.T);
                 typename Pack<R>::T2 o;
-                o.x = pack_axis<R>(cu % g.T, du, dlo, lb);
-                o.y = pack_axis<R>(cv % g.T, dv, dlo, lb);
+                o.x = pack_axis<R>(cu % g.T, du, dlo, lb, ms, kb);
+                o.y = pack_axis<R>(cv % g.T, dv, dlo, lb, ms, kb);
                 offk[k] = o;
             } else {
                 key[u] = g.ntiles;                           // dropped: a position after the valid ones
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kSortThreads) void k_plan_sort_items(PlanGeom g, in
     __shared__ int lfirst[kPiece];      // first tail slot of each length
     __shared__ int lbase[kPiece];       // first entry of each length's tails
     const int TT = g.T * g.T;
-    const int sh = pack_frac_bits<R>(lb) + 1;         // position of the cell bits
+    const int sh = pack_cell_shift<R>(lb);            // position of the cell bits
     int* cnt = sm;             // per-cell counts, then ranks while placing
     int* cinfo = sm + TT;      // per cell: F(c) | (first tail entry) << 16   (both < 2^16: cap <= 16384)
     const int n_items = flags[1];
@@ -579,22 +579,22 @@ hipError_t launch_plan_scan(const PlanGeom& g, const int* tile_count, int* tile_
 }
 
 size_t packed_offset_bytes(bool f64) { return f64 ? sizeof(dev::Pack<double>::T2) : sizeof(dev::Pack<float>::T2); }
-int packed_frac_bits(bool f64, int lb) {
-    return f64 ? dev::pack_frac_bits<double>(lb) : dev::pack_frac_bits<float>(lb);
+int packed_cell_shift(bool f64, int lb) {
+    return f64 ? dev::pack_cell_shift<double>(lb) : dev::pack_cell_shift<float>(lb);
 }
 
 hipError_t launch_plan_scatter(bool f64, const double* uv, const int4* blocks, int nb, const PlanGeom& g,
-                               const int* tile_start, const int* blockhist, double dlo, int lb, int* inv0, void* offk,
-                               hipStream_t s) {
+                               const int* tile_start, const int* blockhist, double dlo, int lb, int ms, int kb,
+                               int* inv0, void* offk, hipStream_t s) {
     if (nb == 0) return hipSuccess;
     const size_t shm = (g.ntiles + 1) * sizeof(int);
     if (f64)
         hipLaunchKernelGGL(dev::k_plan_scatter<double>, dim3(nb), dim3(kPlanThreads), shm, s,
-                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb, ms, kb,
                            inv0, reinterpret_cast<ulonglong2*>(offk));
     else
         hipLaunchKernelGGL(dev::k_plan_scatter<float>, dim3(nb), dim3(kPlanThreads), shm, s,
-                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb,
+                           reinterpret_cast<const double2*>(uv), blocks, nb, g, tile_start, blockhist, dlo, lb, ms, kb,
                            inv0, reinterpret_cast<uint2*>(offk));
     return hipGetLastError();
 }
