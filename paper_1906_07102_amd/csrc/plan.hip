@@ -355,10 +355,15 @@ __global__ __launch_bounds__(kPermThreads) void k_plan_place(const int* __restri
 // pos2 (tile-order position -> entry), pieces[] (first entry, length |
 // cell << 16) and items[i].w = number of pieces. Dropped visibilities
 // (tile-order positions n_valid .. nvis) get pos2 = -1.
+// Ranks within a cell follow the item's tile order in a fixed way: the item
+// is cut into `groups` contiguous chunks, one per group of waves, each with
+// its own LDS cell counters whose bases are the counts of the chunks before
+// it; the waves of one group take their turns in order (a barrier between
+// turns), so with one wave per group no barrier is needed at all.
 constexpr int kSortThreads = 512;     // (256: 124 us, 512: 111 us, 1024: 111 us on the 16.8M-visibility plan)
 template <typename R>
 __global__ __launch_bounds__(kSortThreads) void k_plan_sort_items(PlanGeom g, int4* __restrict__ items,
-                                                         const int* __restrict__ flags, int nvis, int lb,
+                                                         const int* __restrict__ flags, int nvis, int lb, int groups,
                                                          const typename Pack<R>::T2* __restrict__ off0,
                                                          typename Pack<R>::T2* __restrict__ off,
                                                          int* __restrict__ pos2, int2* __restrict__ pieces) {
@@ -369,21 +374,42 @@ __global__ __launch_bounds__(kSortThreads) void k_plan_sort_items(PlanGeom g, in
     __shared__ int lbase[kPiece];       // first entry of each length's tails
     const int TT = g.T * g.T;
     const int sh = pack_cell_shift<R>(lb);            // position of the cell bits
-    int* cnt = sm;             // per-cell counts, then ranks while placing
+    int* cnt = sm;             // per-cell counts
     int* cinfo = sm + TT;      // per cell: F(c) | (first tail entry) << 16   (both < 2^16: cap <= 16384)
+    // per group and cell: counts, then the group's next rank (one group: cnt itself, reset before placing)
+    int* gcnt = groups > 1 ? sm + 2 * TT : sm;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nwaves = blockDim.x >> 6;
+    const int wpg = nwaves / groups;                 // waves per group
+    const int grp = wave / wpg, wig = wave % wpg;
+    int* gc = gcnt + grp * TT;
     const int n_items = flags[1];
     for (int e = flags[2] + blockIdx.x * blockDim.x + threadIdx.x; e < nvis; e += gridDim.x * blockDim.x)
         pos2[e] = -1;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {     // uniform across the workgroup
         const int4 it = items[item];
-        for (int c = threadIdx.x; c < TT; c += blockDim.x) cnt[c] = 0;
+        for (int c = threadIdx.x; c < groups * TT; c += blockDim.x) gcnt[c] = 0;
         if (threadIdx.x < kPiece) lcnt[threadIdx.x] = 0;
         __syncthreads();
-        for (int e = threadIdx.x; e < it.z; e += blockDim.x) {
+        // chunk of each group: a multiple of the group's 64 wpg lanes, the same for all groups
+        const int chunk = ((it.z + groups - 1) / groups + 64 * wpg - 1) / (64 * wpg) * (64 * wpg);
+        const int g0 = grp * chunk, g1 = min(it.z, g0 + chunk);
+        for (int e = g0 + wig * 64 + lane; e < g1; e += 64 * wpg) {
             const typename Pack<R>::T2 r = off0[it.y + e];
-            atomicAdd(&cnt[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
+            atomicAdd(&gc[static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh)], 1);
         }
         __syncthreads();
+        if (groups > 1) {
+            for (int c = threadIdx.x; c < TT; c += blockDim.x) {     // group bases: counts of the chunks before
+                int base = 0;
+                for (int q = 0; q < groups; ++q) {
+                    const int n = gcnt[q * TT + c];
+                    gcnt[q * TT + c] = base;
+                    base += n;
+                }
+                cnt[c] = base;
+            }
+            __syncthreads();
+        }
         // full pieces: exclusive prefix F over cells (each thread a run of cells); tails counted by length
         const int seg = (TT + blockDim.x - 1) / blockDim.x;
         const int c0 = threadIdx.x * seg, c1 = min(TT, c0 + seg);
@@ -415,15 +441,13 @@ __global__ __launch_bounds__(kSortThreads) void k_plan_sort_items(PlanGeom g, in
             if (ln == 63) items[item].w = nf + inc_n;
         }
         __syncthreads();
-        // Tail slots and entry ranks come from LDS cursors; the waves take them in a fixed turn (a barrier
-        // between turns), so that the layout, and with it the summation order of the gridding kernel, is the
-        // same on every run.
-        const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+        // Tail slots come from LDS cursors; the waves take them in a fixed turn (a barrier between turns), so
+        // that the layout, and with it the summation order of the gridding kernel, is the same on every run.
         for (int w = 0; w < nwaves; ++w) {
             if (wave == w) {
                 for (int c = c0; c < c1; ++c) {
                     const int n = cnt[c];
-                    cnt[c] = 0;                          // ranks while placing
+                    if (groups == 1) cnt[c] = 0;         // the group's ranks while placing
                     if (!n) continue;
                     const int f = n / kPiece, t = n % kPiece;
                     const int lc = ((c / g.T) << 8) | (c % g.T);
@@ -441,18 +465,23 @@ __global__ __launch_bounds__(kSortThreads) void k_plan_sort_items(PlanGeom g, in
             __syncthreads();
         }
         const int nf = nf_all;
-        for (int e0 = 0; e0 < it.z; e0 += blockDim.x) {  // uniform across the workgroup
-            const int e = e0 + threadIdx.x;
-            const bool live = e < it.z;
+        const int rounds = chunk / (64 * wpg);
+        for (int rd = 0; rd < rounds; ++rd) {            // uniform across the workgroup
+            const int e = g0 + rd * 64 * wpg + wig * 64 + lane;
+            const bool live = e < g1;
             typename Pack<R>::T2 r;
             int c = 0, rank = 0;
             if (live) {
                 r = off0[it.y + e];
                 c = static_cast<int>(r.y >> sh) * g.T + static_cast<int>(r.x >> sh);
             }
-            for (int w = 0; w < nwaves; ++w) {
-                if (wave == w && live) rank = atomicAdd(&cnt[c], 1);
-                __syncthreads();
+            if (wpg == 1) {                              // the group's counters are the wave's own
+                if (live) rank = atomicAdd(&gc[c], 1);
+            } else {
+                for (int w = 0; w < wpg; ++w) {          // uniform: every group has wpg waves
+                    if (wig == w && live) rank = atomicAdd(&gc[c], 1);
+                    __syncthreads();
+                }
             }
             if (live) {
                 const int ci = cinfo[c];
@@ -614,14 +643,19 @@ hipError_t launch_plan_place(bool f64, const int* inv0, const void* offk, const 
 
 hipError_t launch_plan_sort(bool f64, const PlanGeom& g, int4* items, int max_items, const int* flags, int nvis,
                             int lb, const void* off0, void* off, int* pos2, int2* pieces, hipStream_t s) {
-    const size_t shm = 2 * static_cast<size_t>(g.T) * g.T * sizeof(int);
+    // One counter group per wave while the counters fit in 40 KB with the per-cell arrays (T <= 32),
+    // else one group whose waves take turns.
+    const size_t TT = static_cast<size_t>(g.T) * g.T;
+    const int waves = dev::kSortThreads / 64;
+    const int groups = (2 + waves) * TT * sizeof(int) <= 40 * 1024 ? waves : 1;
+    const size_t shm = (2 + (groups > 1 ? groups : 0)) * TT * sizeof(int);
     const unsigned nb = static_cast<unsigned>(std::max(1, std::min(max_items, 8192)));
     if (f64)
-        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(nb), dim3(dev::kSortThreads), shm, s, g, items, flags, nvis, lb,
+        hipLaunchKernelGGL(dev::k_plan_sort_items<double>, dim3(nb), dim3(dev::kSortThreads), shm, s, g, items, flags, nvis, lb, groups,
                            reinterpret_cast<const ulonglong2*>(off0), reinterpret_cast<ulonglong2*>(off), pos2,
                            pieces);
     else
-        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(nb), dim3(dev::kSortThreads), shm, s, g, items, flags, nvis, lb,
+        hipLaunchKernelGGL(dev::k_plan_sort_items<float>, dim3(nb), dim3(dev::kSortThreads), shm, s, g, items, flags, nvis, lb, groups,
                            reinterpret_cast<const uint2*>(off0), reinterpret_cast<uint2*>(off), pos2,
                            pieces);
     return hipGetLastError();
