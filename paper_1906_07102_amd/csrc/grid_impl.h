@@ -4,6 +4,8 @@
 // parallel.
 #pragma once
 
+#include <type_traits>
+
 #include "dev_common.h"
 
 namespace lmg {
@@ -46,6 +48,7 @@ struct AccF32 {
     using Reg = float2;
     __device__ static void zero_cell(Cell* c) { *c = make_float2(0.f, 0.f); }
     __device__ static void zero(Reg& r) { r = make_float2(0.f, 0.f); }
+    __device__ static void set(Reg& r, float re, float im) { r = make_float2(re, im); }
     __device__ static void add(Reg& r, float re, float im) {
         r.x += re;
         r.y += im;
@@ -84,6 +87,8 @@ struct AccKahan {
         c = (t - s) - y;
         s = t;
     }
+    // the first term of a sum: what kahan() gives from zeros, without the zeros
+    __device__ static void set(Reg& r, float re, float im) { r = make_float4(re, im, 0.f, 0.f); }
     __device__ static void add(Reg& r, float re, float im) {
         kahan(r.x, r.z, re);
         kahan(r.y, r.w, im);
@@ -138,6 +143,7 @@ struct AccF64 {
     using Reg = double2;
     __device__ static void zero_cell(Cell* c) { *c = make_double2(0.0, 0.0); }
     __device__ static void zero(Reg& r) { r = make_double2(0.0, 0.0); }
+    __device__ static void set(Reg& r, double re, double im) { r = make_double2(re, im); }
     __device__ static void add(Reg& r, double re, double im) {
         r.x += re;
         r.y += im;
@@ -254,16 +260,18 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
             for (int pass = 0; pass < NPASS; ++pass) {
                 const int r0 = pass * RG;
                 typename Acc::Reg acc[RG * W];
-#pragma unroll
-                for (int q = 0; q < RG * W; ++q) Acc::zero(acc[q]);
-                for (int j0 = 0; j0 < len; j0 += kB) {
+                // One batch of kB entries from entry j0 of the piece. The first batch sets the accumulators
+                // from its first entry instead of adding to zeros; every lane runs that entry (a lane without
+                // a piece reads entry 0 of the arrays and never flushes), so no accumulator is ever zeroed.
+                auto batch = [&](int j0, auto first) {
+                    constexpr bool kFirst = decltype(first)::value;
                     PT2 dv[kB];
                     VT vv[kB];
                     load_run<kB>(off + pc.x + j0, dv);
                     load_run<kB>(vis + pc.x + j0, vv);
 #pragma unroll
                     for (int u = 0; u < kB; ++u) {
-                        if (j0 + u >= len) break;
+                        if (!(kFirst && u == 0) && j0 + u >= len) break;
                         R cu[W], cv[W];
                         if constexpr (kTab == kTabDirect) {
                             weights_direct<R, W>(static_cast<const double*>(a.coef), dv[u].x, a.Ft, cu);
@@ -280,10 +288,17 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
                             if (r0 + r >= W) break;
                             const R ar = vv[u].x * cv[r0 + r], ai = vv[u].y * cv[r0 + r];
 #pragma unroll
-                            for (int c = 0; c < W; ++c) Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                            for (int c = 0; c < W; ++c) {
+                                if (kFirst && u == 0)
+                                    Acc::set(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                                else
+                                    Acc::add(acc[r * W + c], ar * cu[c], ai * cu[c]);
+                            }
                         }
                     }
-                }
+                };
+                batch(0, std::true_type{});
+                for (int j0 = kB; j0 < len; j0 += kB) batch(j0, std::false_type{});
                 flush_rows<Acc, W, RG>(patch, owner, P, lane, have && len > 0, l, r0, acc);
             }
         }
