@@ -247,13 +247,17 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
         const int4 it = a.items[item];
         constexpr int kB = 4;                               // entries whose loads are issued together
         const int rounds = (it.w + blockDim.x - 1) / blockDim.x;
+        // consecutive pieces go to different waves (a dense cell's full pieces are neighbours, and lanes of
+        // one wave sharing a cell flush in turns); a lane's piece of the next round is loaded a round ahead
+        const int p0 = (threadIdx.x & 63) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+        int2 pc_next = make_int2(0, 0);
+        if (p0 < it.w) pc_next = a.pieces[it.y + p0];
         for (int rd = 0; rd < rounds; ++rd) {               // uniform across the workgroup
-            // consecutive pieces go to different waves (a dense cell's full pieces are neighbours, and
-            // lanes of one wave sharing a cell flush in turns)
-            const int p = rd * blockDim.x + (threadIdx.x & 63) * (blockDim.x >> 6) + (threadIdx.x >> 6);
+            const int p = rd * blockDim.x + p0;
             const bool have = p < it.w;
-            int2 pc = make_int2(0, 0);
-            if (have) pc = a.pieces[it.y + p];
+            const int2 pc = pc_next;
+            pc_next = make_int2(0, 0);
+            if (p + static_cast<int>(blockDim.x) < it.w) pc_next = a.pieces[it.y + p + blockDim.x];
             const int len = pc.y & 0xffff;
             const int l = static_cast<int>(static_cast<unsigned>(pc.y) >> 16);
 #pragma unroll
