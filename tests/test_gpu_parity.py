@@ -125,6 +125,29 @@ def test_grid_edges_wrap_and_ties(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("degree", [0, 1, 3])
+def test_offsets_on_table_nodes_and_midpoints(prec, degree):
+    """Offsets exactly on table nodes and exactly halfway between two (App. F). With M_s = 32 (a 224-entry
+    W = 7 table) both are binary fractions, so the device and the oracle see the same s = M_s x and take the
+    same interval, and for degree 0 the same nearest node (halfway rounds up). delta runs over (-1/2, 1/2],
+    x = delta + 1/2 over (0, 1]: nodes 1 .. 32 (32 is the interval's top end) and midpoints 0.5 .. 31.5."""
+    print(f"table nodes and midpoints prec={prec} degree={degree}", flush=True)
+    otab, gtab, _ = tables(7, degree, table_size=224)
+    assert otab.Ms == 32
+    N = 64
+    f = np.concatenate([-0.5 + np.arange(1, 33) / 32.0, -0.5 + (np.arange(32) + 0.5) / 32.0])
+    rng = np.random.default_rng(61)
+    n = rng.integers(-24, 24, size=(len(f), 2))
+    uv = np.stack([n[:, 0] + f, n[:, 1] + f[rng.permutation(len(f))]], axis=1)
+    vis = rng.standard_normal(len(uv)) + 1j * rng.standard_normal(len(uv))
+    plan, g = gpu_grid(gtab, N, uv, vis, None, prec)
+    assert rel_rms(g, im.grid(uv, vis, None, N, otab)) < TOL[prec]
+    G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    out = plan.degrid(to_dev(G, ctype(prec))).cpu().numpy()
+    assert rel_rms(out, im.degrid(uv, G, otab)) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_empty_and_non_finite(prec):
     otab, gtab, _ = tables(7, 3)
     N = 64
