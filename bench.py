@@ -289,6 +289,17 @@ def _timed(fn, reps, stream=None):
     return e0.elapsed_time(e1) / reps
 
 
+def measured_copy_gbps(reps=10) -> float:
+    """Bandwidth of a plain device copy on this GPU: torch.mul(a, 1.0, out=b) over 1 GiB (1 GiB read and 1 GiB
+    written per pass; the same kernel the byte counters are calibrated on), HIP events over `reps` passes."""
+    import torch
+    a = torch.ones(int(CALIBRATION_BYTES) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    ms = _timed(lambda: torch.mul(a, 1.0, out=b), reps)
+    del a, b
+    return 2.0 * CALIBRATION_BYTES / (ms * 1e-3) / 1e9
+
+
 def precision_study(lmg, case, uv, vis64, reps=5):
     """Dirty images of the workload for W = 3, 5, 7 in the three accumulation modes against the direct DFT on
     the 256 x 256 pixel lattice (every 8th pixel of the retained field) of tests/golden/dft_samples_16m_4096.npy; with the time of one dirty image +
@@ -753,8 +764,13 @@ def main():
     kernels[dom]["avg_ms_timed_region"] = round(dom_avg_s * 1e3, 5)
     ab = algorithmic_bytes(dom, nvis, N, M, cs)
     achieved = ab / dom_avg_s / 1e9
+    copy_gbps = measured_copy_gbps()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, nvis), "kernel": dom}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, nvis), "kernel": dom,
+                "copy_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)}
+    for order in ("caller_order", "plan_order"):
+        grid_degrid_unit[f"copy_frac_{order}"] = round(
+            unit_bytes / (grid_degrid_unit[f"ms_{order}"] * 1e-3) / 1e9 / copy_gbps, 4)
     if args.copy_calibration:
         a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
