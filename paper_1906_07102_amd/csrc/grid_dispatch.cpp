@@ -34,6 +34,16 @@ hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& args, hipStre
     const int64_t tiles = static_cast<int64_t>(a.nchan) * a.trows * a.tcols;
     const bool whole_grid = a.trows == a.ntx && a.tcols == a.ntx && tiles >= 4096;
     a.rows = (tiles > 32768 || whole_grid) ? std::min(a.T, 1024 / a.T) : std::min(a.T, 8);
+    // Whole grids of a batch: runs of grid rows, tile by tile (one cell of a tile per thread), while that
+    // still makes at least 8,192 workgroups.
+    a.rows_kernel = 0;
+    if (a.trows == a.ntx && a.tcols == a.ntx && a.tr0 == 0 && a.tc0 == 0) {
+        const int rr = std::max(1, std::min(a.T, kAssembleThreads / a.T));
+        if (static_cast<int64_t>(a.nchan) * (a.N / rr) >= 8192) {
+            a.rows = rr;
+            a.rows_kernel = 1;
+        }
+    }
     const unsigned nt = static_cast<unsigned>(tiles * (a.T / a.rows));
     if (nt == 0) return hipSuccess;
     switch (prec) {

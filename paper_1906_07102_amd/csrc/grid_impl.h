@@ -325,7 +325,6 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_grid_items(GridArgs a) {
 // returns at once, so cells outside the data's footprint are neither read nor
 // written. One workgroup per a.rows rows of a tile (chosen by the launcher).
 
-constexpr int kAssembleThreads = 256;    // (512 / 1024 threads: band 37 -> 47 / 72 us, batched 0.84 -> 1.19 / 2.19 ms)
 template <typename R, typename Acc>
 __global__ __launch_bounds__(kAssembleThreads) void k_assemble(AssembleArgs a) {
     using VT = typename C2<R>::T;
@@ -359,6 +358,16 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(AssembleArgs a) {
         any = any || i1[s] > i0[s];
     }
     if (a.accumulate && !any) return;                       // uniform across the workgroup
+    if (!any) {                                             // no patch: zeros, two cells per store
+        for (int pair = threadIdx.x; pair < ar * a.T / 2; pair += blockDim.x) {
+            const int lr = rb + (2 * pair) / a.T, lc = (2 * pair) % a.T;
+            VT* dst = grid + static_cast<size_t>(tm * a.T + lr) * a.N + tn * a.T + lc;
+            VT z[2];
+            z[0].x = 0; z[0].y = 0; z[1] = z[0];
+            __builtin_memcpy(dst, z, sizeof(z));
+        }
+        return;
+    }
     for (int cell = threadIdx.x; cell < ar * a.T; cell += blockDim.x) {
         const int lr = rb + cell / a.T, lc = cell % a.T;
         typename Acc::Sum sum;
@@ -373,6 +382,77 @@ __global__ __launch_bounds__(kAssembleThreads) void k_assemble(AssembleArgs a) {
         old.y = 0;
         if (a.accumulate) old = *dst;
         *dst = sum.value(old);
+    }
+}
+
+// Whole grids of many channels: one workgroup per a.rows consecutive grid
+// rows of one channel, which it writes tile by tile along the row, so that a
+// batch of grids takes nchan N / a.rows workgroups instead of one per tile
+// (most tiles of a batch's grids receive no patch, and per-workgroup costs
+// dominate). The item ranges of the two tile rows its cells read (its own
+// and the one above) are staged in LDS once; a tile's ranges are then the
+// same for every lane. Cells sum the same sources in the same order as
+// k_assemble, so the two give the same bits; overwrite (a tile without
+// patches takes zeros two cells per store), or accumulate (such a tile is
+// skipped).
+template <typename R, typename Acc>
+__global__ __launch_bounds__(kAssembleThreads) void k_assemble_rows(AssembleArgs a) {
+    extern __shared__ int rng[];                           // [2][ntx + 1]: item_start of tile rows tm, tm - 1
+    using VT = typename C2<R>::T;
+    using Cell = typename Acc::Cell;
+    const int per_chan = a.N / a.rows;
+    const int chan = blockIdx.x / per_chan;
+    const int r0 = (blockIdx.x % per_chan) * a.rows;       // first grid row (storage order)
+    const int tm = r0 / a.T, rb = r0 % a.T;
+    const int ntiles = a.ntx * a.ntx;
+    const int cbase = chan * ntiles;
+    const int tmu = (tm + a.ntx - 1) % a.ntx;
+    for (int i = threadIdx.x; i <= a.ntx; i += blockDim.x) {
+        rng[i] = a.item_start[cbase + tm * a.ntx + i];
+        rng[a.ntx + 1 + i] = a.item_start[cbase + tmu * a.ntx + i];
+    }
+    __syncthreads();
+    const int* own = rng;
+    const int* up = rng + a.ntx + 1;
+    const int lbT = __builtin_ctz(static_cast<unsigned>(a.T));
+    const int ncell = a.rows << lbT;                       // cells of one tile in the workgroup's rows
+    const int P = a.T + a.W - 1;
+    const int halo = a.W - 1;
+    const Cell* patches = reinterpret_cast<const Cell*>(a.patches);
+    VT* grid = reinterpret_cast<VT*>(a.grid) + static_cast<size_t>(chan) * a.N * a.N + static_cast<size_t>(r0) * a.N;
+    for (int tn = 0; tn < a.ntx; ++tn) {                   // uniform across the workgroup
+        const int tl = (tn + a.ntx - 1) % a.ntx;
+        int i0[4], i1[4];
+        i0[0] = own[tn]; i1[0] = own[tn + 1];              // own tile, left, upper, upper-left
+        i0[1] = own[tl]; i1[1] = own[tl + 1];
+        i0[2] = up[tn];  i1[2] = up[tn + 1];
+        i0[3] = up[tl];  i1[3] = up[tl + 1];
+        const bool any = i1[0] > i0[0] || i1[1] > i0[1] || i1[2] > i0[2] || i1[3] > i0[3];
+        if (!any) {
+            if (a.accumulate) continue;
+            for (int pair = threadIdx.x; pair < ncell / 2; pair += blockDim.x) {
+                VT* dst = grid + static_cast<size_t>((2 * pair) >> lbT) * a.N + (tn << lbT) + ((2 * pair) & (a.T - 1));
+                VT z[2];
+                z[0].x = 0; z[0].y = 0; z[1] = z[0];
+                __builtin_memcpy(dst, z, sizeof(z));
+            }
+            continue;
+        }
+        for (int cell = threadIdx.x; cell < ncell; cell += blockDim.x) {
+            const int lr = rb + (cell >> lbT), lc = cell & (a.T - 1);
+            typename Acc::Sum sum;
+            for (int s = 0; s < 4; ++s) {
+                if ((s == 1 && lc >= halo) || (s == 2 && lr >= halo) || (s == 3 && (lr >= halo || lc >= halo))) continue;
+                const int pr = lr + (s >= 2 ? a.T : 0), pc = lc + ((s & 1) ? a.T : 0);
+                for (int it = i0[s]; it < i1[s]; ++it) sum.add(patches[static_cast<size_t>(it) * P * P + pr * P + pc]);
+            }
+            VT* dst = grid + static_cast<size_t>(cell >> lbT) * a.N + (tn << lbT) + lc;
+            VT old;
+            old.x = 0;
+            old.y = 0;
+            if (a.accumulate) old = *dst;
+            *dst = sum.value(old);
+        }
     }
 }
 
@@ -407,7 +487,13 @@ hipError_t dispatch_grid(const GridArgs& a, hipStream_t s) {
 }
 template <typename R, typename Acc>
 hipError_t assemble(const AssembleArgs& a, unsigned nt, hipStream_t s) {
-    hipLaunchKernelGGL((dev::k_assemble<R, Acc>), dim3(nt), dim3(dev::kAssembleThreads), 0, s, a);
+    if (a.rows_kernel) {
+        const unsigned nb = static_cast<unsigned>(a.nchan) * static_cast<unsigned>(a.N / a.rows);
+        const size_t shm = 2 * (static_cast<size_t>(a.ntx) + 1) * sizeof(int);
+        hipLaunchKernelGGL((dev::k_assemble_rows<R, Acc>), dim3(nb), dim3(kAssembleThreads), shm, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((dev::k_assemble<R, Acc>), dim3(nt), dim3(kAssembleThreads), 0, s, a);
     return hipGetLastError();
 }
 }  // namespace grid_impl
