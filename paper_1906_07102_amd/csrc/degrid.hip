@@ -11,7 +11,7 @@ namespace dev {
 // stores of the results are contiguous across the wave. Entries are sorted
 // by footprint cell, so lanes of a wave mostly share a cell and read the
 // same patch addresses (an LDS broadcast). The cell comes from the packed
-// offset word (bits above F). (Caching a lane's footprint in registers over
+// offset word (the bits above the interval and fraction fields). (Caching a lane's footprint in registers over
 // a run of its visibilities measured slower: the register cost lowers
 // occupancy more than the LDS reads it saves.)
 // Threads per degridding workgroup: larger workgroups spread an item's fixed

@@ -47,7 +47,6 @@ struct AccF32 {
     using Cell = float2;
     using Reg = float2;
     __device__ static void zero_cell(Cell* c) { *c = make_float2(0.f, 0.f); }
-    __device__ static void zero(Reg& r) { r = make_float2(0.f, 0.f); }
     __device__ static void set(Reg& r, float re, float im) { r = make_float2(re, im); }
     __device__ static void add(Reg& r, float re, float im) {
         r.x += re;
@@ -80,7 +79,6 @@ struct AccKahan {
     using Cell = float4;      // (sum re, sum im, comp re, comp im)
     using Reg = float4;       // (s re, s im, c re, c im)
     __device__ static void zero_cell(Cell* c) { *c = make_float4(0.f, 0.f, 0.f, 0.f); }
-    __device__ static void zero(Reg& r) { r = make_float4(0.f, 0.f, 0.f, 0.f); }
     __device__ static void kahan(float& s, float& c, float x) {
         const float y = x - c;
         const float t = s + y;
@@ -142,7 +140,6 @@ struct AccF64 {
     using Cell = double2;
     using Reg = double2;
     __device__ static void zero_cell(Cell* c) { *c = make_double2(0.0, 0.0); }
-    __device__ static void zero(Reg& r) { r = make_double2(0.0, 0.0); }
     __device__ static void set(Reg& r, double re, double im) { r = make_double2(re, im); }
     __device__ static void add(Reg& r, double re, double im) {
         r.x += re;
