@@ -653,8 +653,8 @@ def main():
         print(text, end="")
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported in this build "
-              f"(multi-GPU sharding is a design note only)", file=sys.stderr)
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding over several GPUs is a design note only)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -42,7 +42,7 @@ typedef enum {
     LMG_EWORKSPACE = -2,  /* workspace NULL or smaller than the size query returned */
     LMG_EHIP = -3,        /* a HIP runtime call failed */
     LMG_EDATA = -4,       /* non-finite uv coordinates were met (reported by lmg_plan_check) */
-    LMG_ENOTSUP = -5,     /* a valid request this build does not support (e.g. table too large) */
+    LMG_ENOTSUP = -5,     /* a valid request the library does not support (e.g. an image call on a multi-channel plan) */
     LMG_ENOCONV = -6      /* the table optimiser did not reach its tolerance */
 } lmg_status;
 

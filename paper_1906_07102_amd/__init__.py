@@ -127,7 +127,7 @@ def load():
 
 
 def exported_symbols():
-    """Names the C ABI exports (for the build check)."""
+    """Names the C ABI exports (checked against the header by the library tests)."""
     load()
     return [n for n in dir(_LIB) if n.startswith("lmg_")]
 

@@ -725,7 +725,7 @@ const char* lmg_status_string(lmg_status s) {
         case LMG_EWORKSPACE: return "workspace missing or too small";
         case LMG_EHIP: return "HIP runtime error";
         case LMG_EDATA: return "non-finite uv coordinates were dropped";
-        case LMG_ENOTSUP: return "request not supported by this build";
+        case LMG_ENOTSUP: return "valid request the library does not support";
         case LMG_ENOCONV: return "table optimisation did not converge";
     }
     return "unknown status";
