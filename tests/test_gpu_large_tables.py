@@ -53,3 +53,38 @@ def test_small_tables_need_no_device_copy():
     t = lmg.Table.create(7, 0.25, 300, 3)
     assert t.device_bytes(lmg.F32) == 0 and t.device_bytes(lmg.F64) == 0
     assert t.attach_device(lmg.F64) is None
+
+
+_LIMIT = {}
+
+
+def _limit_table(table_size):
+    """W = 1, degree-1 tables of 2^24 - 1 and 2^24 intervals from the oracle's h (built once each)."""
+    if table_size not in _LIMIT:
+        h = lt.optimal_h(1, 0.25)
+        _LIMIT[table_size] = (lmg.Table.from_h(1, 0.25, table_size, 1, h), h)
+    return _LIMIT[table_size]
+
+
+@pytest.mark.parametrize("prec", [lmg.F32, lmg.F64])
+def test_interval_count_limit_of_the_packed_offsets(prec):
+    """A packed offset word holds the table interval in at most 24 bits (in an FP32 word at T = 32 that
+    leaves 3 fraction bits, still finer in x than 2^-26). A degree-1 table of 2^24 - 1 intervals grids like
+    the oracle's exact kernel (the table's own error, of order M_s^-2, is far below the tolerance); a table
+    of 2^24 intervals is refused with LMG_ENOTSUP."""
+    print(f"interval count limit prec={prec}", flush=True)
+    c = synth.small_case()
+    uvd = dev(c.uv, torch.float64)
+    cdt = torch.complex128 if prec == lmg.F64 else torch.complex64
+    tab, h = _limit_table((1 << 24) - 1)
+    assert tab.Ms == (1 << 24) - 1
+    tab.attach_device(prec)
+    plan = lmg.Plan(tab, c.N, uvd, prec)
+    g = plan.grid(dev(c.vis, cdt)).cpu().numpy()
+    assert rel_rms(g, im.grid(c.uv, c.vis, None, c.N, lt.ExactKernel(1, 0.25, h))) < TOL[prec]
+    big, _ = _limit_table(1 << 24)
+    assert big.Ms == 1 << 24
+    big.attach_device(prec)
+    with pytest.raises(lmg.LmgError) as e:
+        lmg.Plan(big, c.N, uvd, prec)
+    assert e.value.status == -5
