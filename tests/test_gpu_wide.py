@@ -1,4 +1,5 @@
-"""Wide kernels (W = 12, 14): tables whose kernel is App. B's QR least-squares solution.
+"""Wide kernels (W = 12 .. 16, 16 being the widest support the library takes): tables whose kernel is
+App. B's QR least-squares solution.
 
 The library optimises h (Levenberg-Marquardt over QR-solved kernels); the
 oracle builds its table from that h with its own QR solve, and the library
@@ -45,7 +46,7 @@ def wide_tables(W):
 
 
 @pytest.mark.parametrize("prec", [lmg.F32, lmg.F32_KAHAN, lmg.F64])
-@pytest.mark.parametrize("W", [12, 14])
+@pytest.mark.parametrize("W", [12, 14, 15, 16])
 def test_wide_grid_degrid(prec, W):
     print(f"wide grid/degrid W={W} prec={prec}", flush=True)
     otab, gtab, _ = wide_tables(W)
@@ -59,7 +60,7 @@ def test_wide_grid_degrid(prec, W):
     assert rel_rms(v, im.degrid(c.uv, G, otab)) < TOL[prec]
 
 
-@pytest.mark.parametrize("W", [12, 14])
+@pytest.mark.parametrize("W", [12, 14, 16])
 def test_wide_dirty_image(W):
     print(f"wide dirty image W={W}", flush=True)
     otab, gtab, h = wide_tables(W)
