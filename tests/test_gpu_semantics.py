@@ -194,6 +194,43 @@ def test_tile_at_the_support_width(W, tile, prec):
     assert rel_rms(out, im.degrid(uv, G, otab)) < TOL[prec]
 
 
+@pytest.mark.parametrize("tile", [64])
+@pytest.mark.parametrize("prec", [lmg.F32, lmg.F32_KAHAN, lmg.F64])
+def test_large_tiles(tile, prec):
+    """Tiles of 64 cells: the item sort's per-wave cell counters would exceed its LDS budget, so its waves
+    take turns on one set of counters (the sort's other layout path). Dense cells (full 32-entry pieces and
+    tails) over several work items: grid and degrid against the oracle, and a second plan gives the same
+    bits."""
+    print(f"large tiles tile={tile} prec={prec}", flush=True)
+    h = lt.optimal_h(7, 0.25)
+    otab = lt.Table(7, 0.25, 42, 3, lt.table_nodes(h, 7, 0.25, 42, 3))
+    gtab = lmg.Table.from_nodes(7, 0.25, 300, 3, h, otab.nodes)
+    N = 256
+    rng = np.random.default_rng(71 + tile)
+    uv = np.clip(rng.normal(0.0, 12.0, (60000, 2)), -100, 100)
+    vis = rng.standard_normal(len(uv)) + 1j * rng.standard_normal(len(uv))
+    uvd, vd = dev(uv, torch.float64), dev(vis, cdt(prec))
+    plan = lmg.BatchPlan(gtab, N, uvd, [0, len(uv)], prec, tile=tile)
+    assert plan.info()["tile"] == tile
+    g = plan.grid(vd)
+    assert rel_rms(g.cpu().numpy(), im.grid(uv, vis, None, N, otab)) < TOL[prec]
+    G = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    out = plan.degrid(dev(G, cdt(prec))).cpu().numpy()
+    assert rel_rms(out, im.degrid(uv, G, otab)) < TOL[prec]
+    again = lmg.BatchPlan(gtab, N, uvd, [0, len(uv)], prec, tile=tile)
+    assert torch.equal(again.grid(vd), g)
+
+
+def test_tile_whose_patch_exceeds_lds_is_refused():
+    """A 128-cell tile at W = 7 needs a (128 + 6)^2-cell gridding patch, more LDS than a workgroup has: the
+    plan is refused with LMG_ENOTSUP rather than built."""
+    gtab = lmg.Table.create(7, 0.25, 300, 3)
+    uv = dev(np.random.default_rng(72).uniform(-50, 50, (100, 2)), torch.float64)
+    with pytest.raises(lmg.LmgError) as e:
+        lmg.BatchPlan(gtab, 256, uv, [0, 100], lmg.F32, tile=128)
+    assert e.value.status == -5
+
+
 def test_tile_override_below_the_support_is_raised():
     """LMG_TILE below W is raised to the smallest power of two >= W, and the grid stays right."""
     os.environ["LMG_TILE"] = "8"
