@@ -147,6 +147,30 @@ def test_offsets_on_table_nodes_and_midpoints(prec, degree):
     assert rel_rms(out, im.degrid(uv, G, otab)) < TOL[prec]
 
 
+@pytest.mark.parametrize("prec", [lmg.F32, lmg.F64])
+def test_largest_grid(prec):
+    """N = 8192, the largest grid the library takes (the plan's tiles are then 64 cells: at most 128 x 128
+    tiles): 20,000 visibilities over the whole grid, wrapping at its edges. Grid cells sampled inside the
+    data footprint against the oracle's sums by the definition (Eq. 5), and degridding of a random grid."""
+    print(f"largest grid prec={prec}", flush=True)
+    otab, gtab, _ = tables(7, 3)
+    N = 8192
+    rng = np.random.default_rng(81)
+    uv = rng.uniform(-N / 2, N / 2, (20000, 2))
+    vis = rng.standard_normal(len(uv)) + 1j * rng.standard_normal(len(uv))
+    plan, g = gpu_grid(gtab, N, uv, vis, None, prec)
+    assert plan.info()["tile"] == 64
+    cu, cv = im.tap_geometry(uv[:, 0], 7)[0], im.tap_geometry(uv[:, 1], 7)[0]
+    k = rng.integers(0, len(uv), 500)
+    cells = np.stack([(cv[k] + N // 2 + rng.integers(0, 7, 500)) % N,
+                      (cu[k] + N // 2 + rng.integers(0, 7, 500)) % N], axis=1)
+    ref = im.grid_cells(uv, vis, None, N, otab, cells)
+    assert rel_rms(g[cells[:, 0], cells[:, 1]], ref) < TOL[prec]
+    G = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))).astype(np.complex64)
+    out = plan.degrid(to_dev(G, ctype(prec))).cpu().numpy()
+    assert rel_rms(out, im.degrid(uv, G.astype(np.complex128), otab)) < TOL[prec]
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_empty_and_non_finite(prec):
     otab, gtab, _ = tables(7, 3)
