@@ -1,4 +1,4 @@
-// Centred 2D FFT passes (Stockham, LDS-resident rows) with the correction,
+// Centred 2D FFT passes (Stockham radix 8, LDS-resident rows) with the correction,
 // crop and zero pad fused into their loads and stores.
 #include "dev_common.h"
 
@@ -8,31 +8,36 @@ namespace dev {
 // ------------------------------------------------------------------ FFT
 // One pass of the centred 2D transform: ROWS rows of `src` are each loaded
 // into an N-point buffer in LDS (`in_count` values placed from position
-// `in_pos`, zeros elsewhere), transformed with a Stockham radix-4 (plus one
-// radix-2 when log2 N is odd) FFT of sign `sign`, and the outputs at
-// positions [out_pos, out_pos + out_count) are written transposed into `dst`
-// (dst row = output position, dst column = source row). Centring: input
-// position s is multiplied by (-1)^s and output position r by (-1)^r, so
-// positions are indices shifted by N/2. Optional real factors: h_in[s] on
-// inputs, h_out[r] on outputs, h_row[row + row_off] on a whole row.
+// `in_pos`, zeros elsewhere), transformed with Stockham radix-8 stages (plus
+// one radix-4 or radix-2 stage when log2 N is not a multiple of 3) of sign
+// `sign`, and the outputs at positions [out_pos, out_pos + out_count) are
+// written transposed into `dst` (dst row = output position, dst column =
+// source row). Centring: input position s is multiplied by (-1)^s and output
+// position r by (-1)^r, so positions are indices shifted by N/2. Optional real
+// factors: h_in[s] on inputs, h_out[r] on outputs, h_row[row + row_off] on a
+// whole row.
+//
+// A radix-8 stage has N/8 butterflies per row, so a two-row workgroup of
+// 1,024 threads transforms 4,096-point rows with one butterfly per thread and
+// four stages (eight barriers) instead of six radix-4 stages (twelve). The
+// four passes of a 4096^2 image take about 145 us against 177 us with radix
+// 4, and 165 us with one row per workgroup.
 template <int N, int ROWS>
 struct FftShape {
     static constexpr int kLog2 = __builtin_ctz(N);
-    static constexpr int kPass4 = kLog2 / 2;
-    static constexpr bool kPass2 = (kLog2 & 1) != 0;
-    static constexpr int kThreads = (ROWS * N / 4) < 1024 ? (ROWS * N / 4 > 0 ? ROWS * N / 4 : 1) : 1024;
-    static constexpr int kB4 = ROWS * N / 4 / kThreads;   // radix-4 butterflies per thread per pass
-    static constexpr int kB2 = ROWS * N / 2 / kThreads;
+    static constexpr int kPass8 = kLog2 / 3;
+    static constexpr int kRem = kLog2 % 3;   // 2: a final radix-4 stage, 1: a final radix-2 stage
+    static constexpr int kThreads = (ROWS * N / 8) < 1024 ? (ROWS * N / 8 > 0 ? ROWS * N / 8 : 1) : 1024;
     static constexpr int kQuarter = N / 4 > 0 ? N / 4 : 1;
 };
 
 // Twiddles: with TW_LDS a quarter-wave table (cos, sin)(2 pi u / N), u < N / 4,
 // is staged in LDS after the rows and the other quadrants follow by symmetry;
 // otherwise they come from the global table (cos, -sin)(2 pi t / N). In the
-// middle radix-4 stages the lanes of a wave read entries 16 to 256 apart, all
-// in one LDS bank; entry u is therefore stored at tw_slot(u) = u + u / 32,
-// which spreads those reads over distinct banks (passes 3-4 % faster), when
-// the padded table still fits beside the rows (PAD).
+// middle stages the lanes of a wave read entries a multiple of 8 apart, which
+// share few LDS banks; entry u is therefore stored at tw_slot(u) = u + u / 32,
+// which spreads those reads over distinct banks, when the padded table still
+// fits beside the rows (PAD).
 template <bool PAD>
 __device__ __forceinline__ int tw_slot(int u) { return PAD ? u + (u >> 5) : u; }
 
@@ -52,28 +57,174 @@ __device__ __forceinline__ void twiddle(const typename C2<R>::T* __restrict__ tw
     }
 }
 
-// LDS of one pass: ROWS rows, plus the quarter-wave twiddle table when it fits.
+// LDS of one pass: ROWS rows, then the quarter-wave twiddle table when it
+// fits. Rows hold one pad element after every 16 (ROW_PAD) when that still
+// fits: the first radix-8 stage stores each thread's eight outputs to
+// consecutive positions, so the lanes of a wave store 8 elements apart, into
+// few LDS banks, and the pad spreads them (four passes about 145 us against 153 us
+// unpadded).
 template <typename R, int N, int ROWS>
 struct FftLds {
-    static constexpr size_t kRows = static_cast<size_t>(ROWS) * N * sizeof(typename C2<R>::T);
-    static constexpr size_t kTwPlain = static_cast<size_t>(FftShape<N, ROWS>::kQuarter) * sizeof(typename C2<R>::T);
-    static constexpr size_t kTwPadded =
-        static_cast<size_t>(FftShape<N, ROWS>::kQuarter + FftShape<N, ROWS>::kQuarter / 32) * sizeof(typename C2<R>::T);
+    static constexpr size_t kEl = sizeof(typename C2<R>::T);
+    static constexpr size_t kQ = FftShape<N, ROWS>::kQuarter;
+    static constexpr size_t kTwPadded = (kQ + kQ / 32) * kEl;
+    static constexpr bool kRowPad = N >= 16 && static_cast<size_t>(ROWS) * (N + N / 16) * kEl + kTwPadded <= 160 * 1024;
+    static constexpr int kPitch = kRowPad ? N + N / 16 : N;      // elements from one row to the next
+    static constexpr size_t kRows = static_cast<size_t>(ROWS) * kPitch * kEl;
     static constexpr bool kTwPad = kRows + kTwPadded <= 160 * 1024;
-    static constexpr size_t kTw = kTwPad ? kTwPadded : kTwPlain;
+    static constexpr size_t kTw = kTwPad ? kTwPadded : kQ * kEl;
     static constexpr bool kTwLds = N >= 16 && kRows + kTw <= 160 * 1024;
     static constexpr size_t kBytes = kRows + (kTwLds ? kTw : 0);
 };
+
+// LDS slot of row position s.
+template <bool PAD>
+__device__ __forceinline__ int row_slot(int s) { return PAD ? s + (s >> 4) : s; }
+// Slot of position base + r * STEP, given pbase = row_slot(base): a step that is a
+// multiple of 16 carries whole pad elements along.
+template <bool PAD, int STEP>
+__device__ __forceinline__ int row_slot_step(int base, int pbase, int r) {
+    if constexpr (!PAD) return base + r * STEP;
+    else if constexpr (STEP % 16 == 0) return pbase + r * (STEP + STEP / 16);
+    else return row_slot<true>(base + r * STEP);
+}
+
+template <typename VT>
+__device__ __forceinline__ VT cadd(VT a, VT b) {
+    VT o;
+    o.x = a.x + b.x;
+    o.y = a.y + b.y;
+    return o;
+}
+template <typename VT>
+__device__ __forceinline__ VT csub(VT a, VT b) {
+    VT o;
+    o.x = a.x - b.x;
+    o.y = a.y - b.y;
+    return o;
+}
+
+// In-place DFT of RAD = 2, 4 or 8 points with exponent sign sg:
+// v[k] <- sum_n v[n] e^{sg 2 pi i k n / RAD}. Eight points split into the
+// 4-point DFTs of the even and the odd inputs, joined by e^{sg 2 pi i k / 8}.
+template <typename R, int RAD>
+__device__ __forceinline__ void small_dft(typename C2<R>::T* v, R sg) {
+    using VT = typename C2<R>::T;
+    if constexpr (RAD == 2) {
+        const VT a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (RAD == 4) {
+        const VT t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]), t2 = cadd(v[1], v[3]);
+        VT t3;
+        t3.x = -sg * (v[1].y - v[3].y);                   // (v1 - v3) (sign i)
+        t3.y = sg * (v[1].x - v[3].x);
+        v[0] = cadd(t0, t2);
+        v[1] = cadd(t1, t3);
+        v[2] = csub(t0, t2);
+        v[3] = csub(t1, t3);
+    } else {
+        static_assert(RAD == 8, "radix 2, 4 or 8");
+        VT e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        small_dft<R, 4>(e, sg);
+        small_dft<R, 4>(o, sg);
+        const R h = static_cast<R>(0.70710678118654752440);   // cos(pi / 4)
+        VT w;
+        w.x = h * (o[1].x - sg * o[1].y);                     // o1 (1 + sign i) / sqrt 2
+        w.y = h * (o[1].y + sg * o[1].x);
+        o[1] = w;
+        w.x = -sg * o[2].y;                                   // o2 (sign i)
+        w.y = sg * o[2].x;
+        o[2] = w;
+        w.x = -h * (o[3].x + sg * o[3].y);                    // o3 (-1 + sign i) / sqrt 2
+        w.y = h * (sg * o[3].x - o[3].y);
+        o[3] = w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = cadd(e[k], o[k]);
+            v[k + 4] = csub(e[k], o[k]);
+        }
+    }
+}
+
+// One Stockham stage of radix RAD on every row of the workgroup, after stages
+// that have combined Ns = 2^LNS points: butterfly j of a row reads positions
+// j + r N / RAD, twists them by e^{sign i 2 pi r (j mod Ns) / (RAD Ns)}, and
+// after a barrier stores its outputs to positions
+// (j - j mod Ns) RAD + j mod Ns + r Ns.
+template <typename R, int N, int ROWS, int RAD, int LNS>
+__device__ __forceinline__ void stockham_stage(typename C2<R>::T* buf, const typename C2<R>::T* twq,
+                                               const typename C2<R>::T* tw, R sg) {
+    using VT = typename C2<R>::T;
+    using L = FftLds<R, N, ROWS>;
+    constexpr int NT = FftShape<N, ROWS>::kThreads;
+    constexpr bool PR = L::kRowPad;
+    constexpr int Ns = 1 << LNS;
+    constexpr int nb = N / RAD;
+    constexpr int KB = ROWS * nb / NT;   // butterflies per thread
+    static_assert(KB >= 1 && KB * NT == ROWS * nb, "butterflies per thread");
+    constexpr int stride = N / (Ns * RAD);
+    VT hold[RAD * KB];
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+        const int b = threadIdx.x + q * NT;
+        const int rr = b / nb, j = b % nb;
+        const int jm = j & (Ns - 1);
+        const VT* row = buf + rr * L::kPitch;
+        const int pj = row_slot<PR>(j);
+        VT v[RAD];
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) {
+            VT x = row[row_slot_step<PR, nb>(j, pj, r)];
+            if (LNS > 0 && r) {                        // the first stage's twists are all 1
+                R c, sn;
+                // each twiddle from the table (deriving the others as powers of one is faster but
+                // doubles the rounding floor of an FP32 4096-point transform)
+                twiddle<R, N, L::kTwLds, L::kTwPad>(twq, tw, r * jm * stride, c, sn);
+                sn *= sg;
+                const R xr = x.x * c - x.y * sn;
+                x.y = x.x * sn + x.y * c;
+                x.x = xr;
+            }
+            v[r] = x;
+        }
+        small_dft<R, RAD>(v, sg);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) hold[RAD * q + r] = v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < KB; ++q) {
+        const int b = threadIdx.x + q * NT;
+        const int rr = b / nb, j = b % nb;
+        const int jm = j & (Ns - 1);
+        VT* row = buf + rr * L::kPitch;
+        const int d = (j - jm) * RAD + jm;
+        const int pd = row_slot<PR>(d);
+#pragma unroll
+        for (int r = 0; r < RAD; ++r) row[row_slot_step<PR, Ns>(d, pd, r)] = hold[RAD * q + r];
+    }
+    __syncthreads();
+}
+
+template <typename R, int N, int ROWS, int P>
+__device__ __forceinline__ void radix8_stages(typename C2<R>::T* buf, const typename C2<R>::T* twq,
+                                              const typename C2<R>::T* tw, R sg) {
+    if constexpr (P < FftShape<N, ROWS>::kPass8) {
+        stockham_stage<R, N, ROWS, 8, 3 * P>(buf, twq, tw, sg);
+        radix8_stages<R, N, ROWS, P + 1>(buf, twq, tw, sg);
+    }
+}
 
 template <typename R, int N, int ROWS>
 __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     using VT = typename C2<R>::T;
     using S = FftShape<N, ROWS>;
-    constexpr bool kTwLds = FftLds<R, N, ROWS>::kTwLds;
+    using L = FftLds<R, N, ROWS>;
     constexpr int NT = S::kThreads;
     VT* buf = reinterpret_cast<VT*>(smem);
-    VT* twq = buf + ROWS * N;
+    VT* twq = buf + ROWS * L::kPitch;
     // Consecutive row blocks go to one XCD, so that its L2 gathers the narrow transposed writes of
     // neighbouring blocks into whole lines.
     const int row0 = xcd_chunk(blockIdx.x, gridDim.x) * ROWS;
@@ -97,105 +248,27 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
             v.x *= f;
             v.y *= f;
         }
-        buf[rr * N + s] = v;
+        buf[rr * L::kPitch + row_slot<L::kRowPad>(s)] = v;
     }
-    if constexpr (kTwLds) {
+    if constexpr (L::kTwLds) {
         for (int u = threadIdx.x; u < N / 4; u += NT) {
             VT t = reinterpret_cast<const VT*>(a.twiddle)[u];
             t.y = -t.y;
-            twq[tw_slot<FftLds<R, N, ROWS>::kTwPad>(u)] = t;
+            twq[tw_slot<L::kTwPad>(u)] = t;
         }
     }
     __syncthreads();
     const R sg = static_cast<R>(a.sign);
-    int Ns = 1;
-#pragma unroll 1
-    for (int pass = 0; pass < S::kPass4; ++pass) {
-        constexpr int nb = N / 4;
-        const int stride = N / (Ns * 4);
-        VT hold[4 * S::kB4];
-#pragma unroll
-        for (int q = 0; q < S::kB4; ++q) {
-            const int b = threadIdx.x + q * NT;
-            const int rr = b / nb, j = b % nb;
-            const int jm = j % Ns;
-            // each twiddle from the table (deriving w^2 and w^3 as products of w is 6 % faster here
-            // but doubles the rounding floor of an FP32 4096-point transform)
-            VT v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                VT x = buf[rr * N + j + r * nb];
-                if (r) {
-                    R c, sn;
-                    twiddle<R, N, kTwLds, FftLds<R, N, ROWS>::kTwPad>(twq, tw, (r * jm * stride) & (N - 1), c, sn);
-                    sn *= sg;                                  // e^{sign i 2 pi r jm / (4 Ns)}
-                    const R xr = x.x * c - x.y * sn;
-                    x.y = x.x * sn + x.y * c;
-                    x.x = xr;
-                }
-                v[r] = x;
-            }
-            VT t0, t1, t2, t3;
-            t0.x = v[0].x + v[2].x; t0.y = v[0].y + v[2].y;
-            t1.x = v[0].x - v[2].x; t1.y = v[0].y - v[2].y;
-            t2.x = v[1].x + v[3].x; t2.y = v[1].y + v[3].y;
-            const R dx = v[1].x - v[3].x, dy = v[1].y - v[3].y;
-            t3.x = -sg * dy; t3.y = sg * dx;                       // (v1 - v3) (sign i)
-            hold[4 * q + 0].x = t0.x + t2.x; hold[4 * q + 0].y = t0.y + t2.y;
-            hold[4 * q + 1].x = t1.x + t3.x; hold[4 * q + 1].y = t1.y + t3.y;
-            hold[4 * q + 2].x = t0.x - t2.x; hold[4 * q + 2].y = t0.y - t2.y;
-            hold[4 * q + 3].x = t1.x - t3.x; hold[4 * q + 3].y = t1.y - t3.y;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < S::kB4; ++q) {
-            const int b = threadIdx.x + q * NT;
-            const int rr = b / nb, j = b % nb;
-            const int dst = (j / Ns) * Ns * 4 + (j % Ns);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) buf[rr * N + dst + r * Ns] = hold[4 * q + r];
-        }
-        __syncthreads();
-        Ns *= 4;
-    }
-    if constexpr (S::kPass2) {
-        constexpr int nb = N / 2;
-        const int stride = N / (Ns * 2);
-        VT hold[2 * S::kB2];
-#pragma unroll
-        for (int q = 0; q < S::kB2; ++q) {
-            const int b = threadIdx.x + q * NT;
-            const int rr = b / nb, j = b % nb;
-            const int jm = j % Ns;
-            const VT x0 = buf[rr * N + j];
-            VT x = buf[rr * N + j + nb];
-            R c, sn;
-            twiddle<R, N, kTwLds, FftLds<R, N, ROWS>::kTwPad>(twq, tw, (jm * stride) & (N - 1), c, sn);
-            sn *= sg;
-            const R xr = x.x * c - x.y * sn;
-            x.y = x.x * sn + x.y * c;
-            x.x = xr;
-            hold[2 * q].x = x0.x + x.x; hold[2 * q].y = x0.y + x.y;
-            hold[2 * q + 1].x = x0.x - x.x; hold[2 * q + 1].y = x0.y - x.y;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < S::kB2; ++q) {
-            const int b = threadIdx.x + q * NT;
-            const int rr = b / nb, j = b % nb;
-            const int dst = (j / Ns) * Ns * 2 + (j % Ns);
-            buf[rr * N + dst] = hold[2 * q];
-            buf[rr * N + dst + Ns] = hold[2 * q + 1];
-        }
-        __syncthreads();
-    }
+    radix8_stages<R, N, ROWS, 0>(buf, twq, tw, sg);
+    if constexpr (S::kRem == 2) stockham_stage<R, N, ROWS, 4, 3 * S::kPass8>(buf, twq, tw, sg);
+    if constexpr (S::kRem == 1) stockham_stage<R, N, ROWS, 2, 3 * S::kPass8>(buf, twq, tw, sg);
     VT* dst = reinterpret_cast<VT*>(a.dst);
     for (int idx = threadIdx.x; idx < a.out_count * ROWS; idx += NT) {
         const int o = idx / ROWS, rr = idx % ROWS;
         const int row = row0 + rr;
         if (row >= a.nrows) continue;
         const int r = a.out_pos + o;
-        VT v = buf[rr * N + r];
+        VT v = buf[rr * L::kPitch + row_slot<L::kRowPad>(r)];
         R f = (r & 1) ? R(-1) : R(1);
         if (h_out) f *= h_out[r];
         v.x *= f;
