@@ -233,22 +233,37 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
     const R* h_in = reinterpret_cast<const R*>(a.h_in);
     const R* h_out = reinterpret_cast<const R*>(a.h_out);
     const R* h_row = reinterpret_cast<const R*>(a.h_row);
-    for (int idx = threadIdx.x; idx < ROWS * N; idx += NT) {
+    // Each thread loads kPer elements. All guarded loads (values and factors) are issued before any is
+    // used, so a thread waits on memory once rather than once per element.
+    constexpr int kPer = ROWS * N / NT;
+    static_assert(kPer * NT == ROWS * N, "elements per thread");
+    VT v[kPer];
+    R hin[kPer], hrow[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * NT;
         const int rr = idx / N, s = idx % N;
         const int row = row0 + rr;
-        VT v;
-        v.x = 0;
-        v.y = 0;
         const int c = s - a.in_pos;
+        v[q].x = 0;
+        v[q].y = 0;
+        hin[q] = 1;
+        hrow[q] = 1;
         if (row < a.nrows && c >= 0 && c < a.in_count) {
-            v = src[static_cast<size_t>(row) * a.src_pitch + c];
-            R f = (s & 1) ? R(-1) : R(1);
-            if (h_in) f *= h_in[s];
-            if (h_row) f *= h_row[row + a.row_off];
-            v.x *= f;
-            v.y *= f;
+            v[q] = src[static_cast<size_t>(row) * a.src_pitch + c];
+            if (h_in) hin[q] = h_in[s];
+            if (h_row) hrow[q] = h_row[row + a.row_off];
         }
-        buf[rr * L::kPitch + row_slot<L::kRowPad>(s)] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * NT;
+        const int rr = idx / N, s = idx % N;
+        const R f = ((s & 1) ? R(-1) : R(1)) * hin[q] * hrow[q];
+        VT x = v[q];
+        x.x *= f;
+        x.y *= f;
+        buf[rr * L::kPitch + row_slot<L::kRowPad>(s)] = x;
     }
     if constexpr (L::kTwLds) {
         for (int u = threadIdx.x; u < N / 4; u += NT) {
@@ -262,18 +277,28 @@ __global__ __launch_bounds__((FftShape<N, ROWS>::kThreads)) void k_fft_pass(FftA
     radix8_stages<R, N, ROWS, 0>(buf, twq, tw, sg);
     if constexpr (S::kRem == 2) stockham_stage<R, N, ROWS, 4, 3 * S::kPass8>(buf, twq, tw, sg);
     if constexpr (S::kRem == 1) stockham_stage<R, N, ROWS, 2, 3 * S::kPass8>(buf, twq, tw, sg);
+    // Store phase: out_count * ROWS <= kPer * NT outputs; the factors' loads again issued first.
     VT* dst = reinterpret_cast<VT*>(a.dst);
-    for (int idx = threadIdx.x; idx < a.out_count * ROWS; idx += NT) {
+    const int nout = a.out_count * ROWS;
+    R hout[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * NT;
+        hout[q] = 1;
+        if (h_out && idx < nout) hout[q] = h_out[a.out_pos + idx / ROWS];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int idx = threadIdx.x + q * NT;
         const int o = idx / ROWS, rr = idx % ROWS;
         const int row = row0 + rr;
-        if (row >= a.nrows) continue;
+        if (idx >= nout || row >= a.nrows) continue;
         const int r = a.out_pos + o;
-        VT v = buf[rr * L::kPitch + row_slot<L::kRowPad>(r)];
-        R f = (r & 1) ? R(-1) : R(1);
-        if (h_out) f *= h_out[r];
-        v.x *= f;
-        v.y *= f;
-        dst[static_cast<size_t>(o) * a.dst_pitch + row] = v;
+        VT x = buf[rr * L::kPitch + row_slot<L::kRowPad>(r)];
+        const R f = ((r & 1) ? R(-1) : R(1)) * hout[q];
+        x.x *= f;
+        x.y *= f;
+        dst[static_cast<size_t>(o) * a.dst_pitch + row] = x;
     }
 }
 
