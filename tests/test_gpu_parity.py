@@ -227,10 +227,12 @@ def sampled_centred_dft(G, n, N, sign, k1, k2):
 
 
 @pytest.mark.parametrize("prec", [lmg.F32, lmg.F64])
-@pytest.mark.parametrize("N", [64, 128, 4096, 8192])
+@pytest.mark.parametrize("N", [4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192])
 def test_fft2_centred(prec, N):
-    """N = 8192 also covers, in FP64, the pass whose quarter-wave twiddle table fits LDS only unpadded; it is
-    checked on 48 x 48 sampled outputs against a direct sum."""
+    """Every supported N: log2 N a multiple of 3 (radix-8 stages only), or one more radix-2 or radix-4 stage;
+    the smallest sizes run with unpadded rows and a few threads per workgroup. N = 8192 also covers, in FP64,
+    the pass whose rows are unpadded and whose quarter-wave twiddle table fits LDS only unpadded; it is checked
+    on 48 x 48 sampled outputs against a direct sum."""
     print(f"fft2 prec={prec} N={N}", flush=True)
     rng = np.random.default_rng(N)
     n = min(N, 512)
