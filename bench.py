@@ -485,7 +485,7 @@ def _dirty_from_grid(lmg, G, hpix, M):
     return F[sl, sl].to(torch.complex128) * h[:, None] * h[None, :]
 
 
-def north_star_comparison(lmg, case, uv16, vis16, reps=3):
+def equal_misfit_comparison(lmg, case, uv16, vis16, reps=3):
     """The batched, differentiable, compensated-FP32 form against the plain one-channel FP64 path, at equal
     misfit against the direct DFT.
 
@@ -547,7 +547,7 @@ def north_star_comparison(lmg, case, uv16, vis16, reps=3):
         "ms_256_single_channel_fp64": round(ms_s, 4), "speedup": round(ms_s / ms_b, 2),
         "dft_misfit_kahan_channels_0_85_170_255": mis_k, "dft_misfit_fp64_channels_0_85_170_255": mis_64,
     }
-    print(f"# north star W=5: batched kahan {ms_b:.2f} ms, 256 x fp64 {ms_s:.2f} ms; misfit {mis_k} vs {mis_64}",
+    print(f"# equal misfit W=5: batched kahan {ms_b:.2f} ms, 256 x fp64 {ms_s:.2f} ms; misfit {mis_k} vs {mis_64}",
           file=sys.stderr, flush=True)
     del bplan, singles, G32, G64, grad64
     torch.cuda.synchronize()
@@ -584,7 +584,7 @@ def north_star_comparison(lmg, case, uv16, vis16, reps=3):
         "nvis": len(case.uv), "ms_differentiable_kahan": round(ms_k7, 4), "ms_fp64": round(ms_64, 4),
         "speedup": round(ms_64 / ms_k7, 3), "dft_misfit_kahan": mis[0], "dft_misfit_fp64": mis[1],
     }
-    print(f"# north star W=7: kahan {ms_k7:.3f} ms, fp64 {ms_64:.3f} ms; misfit {mis}", file=sys.stderr,
+    print(f"# equal misfit W=7: kahan {ms_k7:.3f} ms, fp64 {ms_64:.3f} ms; misfit {mis}", file=sys.stderr,
           flush=True)
     out["pairing"] = ("W = 5: both forms reach the method's own misfit (equal to 3 digits on four channels); "
                       "W = 7: FP64 needs the same W to stay at or below the compensated form's misfit, and "
@@ -828,7 +828,7 @@ def main():
                         ("interpolation_study", lambda: interpolation_study(lmg, case.N, uv, vis.to(torch.complex128))),
                         ("large_table_study", lambda: large_table_study(lmg, case.N, uv, vis.to(torch.complex128))),
                         ("multichannel", lambda: multichannel_study(lmg)),
-                        ("north_star_comparison", lambda: north_star_comparison(lmg, case, uv, vis))):
+                        ("equal_misfit_comparison", lambda: equal_misfit_comparison(lmg, case, uv, vis))):
             if args.only_studies and key not in args.only_studies.split(","):
                 continue
             try:

@@ -8,7 +8,7 @@ over visibilities, (11) its integral form over the fractional offset nu,
 (12)-(15) optimal correction, (16) integrated misfit E, (17)-(19) normal
 equations A C(nu) = B(nu).
 
-Conventions used here (the readings are listed in the design doc):
+Conventions used here (readings where the paper leaves a choice):
 
 * A visibility at coordinate u (in grid cells) is spread onto the W cells
   n_first .. n_first+W-1 with n_first = ceil(u - W/2); this is exactly the set

@@ -6,7 +6,7 @@ measures the least-misfit functions against (Sec. 1, where the spheroidal
 family with weighting exponent alpha is introduced; Sec. 2.2, map error for
 W = 6 .. 14; Sec. 4, alias suppression).
 
-Definition used (readings, listed in the design doc):
+Definition used (readings where the paper leaves a choice):
 
 * For support W (cells) the gridding function is C(u) = (1 - eta^2) psi(eta)
   with eta = 2 u / W for |u| < W/2 and zero outside, where psi is the
