@@ -48,7 +48,8 @@ typedef enum {
 
 typedef enum {
     LMG_F32 = 0,        /* complex64 data, plain FP32 accumulation */
-    LMG_F32_KAHAN = 1,  /* complex64 data, compensated (two-float) FP32 accumulation */
+    LMG_F32_KAHAN = 1,  /* complex64 data, compensated FP32 tile sums: each piece (at most 32 visibilities of
+                           one cell) summed in FP32, the tile sums kept as (hi, lo) pairs by TwoSum */
     LMG_F64 = 2         /* complex128 data, FP64 throughout */
 } lmg_precision;
 
@@ -212,7 +213,7 @@ lmg_status lmg_plan_scratch_size(const lmg_plan* p, int op, size_t* bytes);
  * channels) can be summed into one grid: Eq. 5 is a sum over k. Any other
  * value: LMG_EINVAL. vis: device complex (nvis), w: device float32 (nvis) or
  * NULL for unit weights. The sum is computed in the plan's precision (FP32,
- * compensated FP32 with (hi, lo) pairs, or FP64) in an order fixed by the
+ * compensated FP32 tile sums with (hi, lo) pairs, or FP64) in an order fixed by the
  * plan, so repeated calls on the same plan and data give identical bits, and
  * so do plans built again from the same coordinates. */
 lmg_status lmg_grid_planned(const lmg_plan* p, const void* vis, const float* w, void* grid, int accumulate,

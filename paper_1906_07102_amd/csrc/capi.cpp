@@ -130,15 +130,20 @@ int fit_tile(int T, int N, lmg_precision prec, int W, int Ms) {
 int fit_waves(int T, lmg_precision prec, int W, int Ms) {
     const int forced = env_int("LMG_GRID_WAVES", 0);
     if (forced >= 1 && forced <= kMaxGridWaves && grid_lds_bytes(prec, W, T, Ms, forced) <= kMaxDynLds) return forced;
-    // Waves per compute unit the kernel's registers allow: about 3 per SIMD for plain FP32 (W x W
-    // complex accumulators), 1 for the compensated and FP64 forms (twice the accumulator registers).
-    const int by_registers = prec == LMG_F32 ? 12 : 4;
+    // Waves per compute unit the kernel's registers allow: about 3 per SIMD for plain and compensated
+    // FP32 (W x W complex FP32 accumulators), 1 for FP64 (twice the accumulator registers).
+    const int by_registers = prec == LMG_F64 ? 4 : 12;
+    // The compensated form's (hi, lo) patch cells make LDS the limit, and 1, 2 or 3 waves per workgroup often
+    // give a compute unit the same number of waves; there, more waves per workgroup measured faster up to 3
+    // at W >= 7 (0.456 / 0.380 / 0.318 ms on 16.8M visibilities at W = 7) and up to 2 below (0.269 / 0.211 /
+    // 0.228 ms at W = 5).
+    const int prefer = prec == LMG_F32_KAHAN ? (W >= 7 ? 3 : 2) : 1;
     int best = 1, best_total = 0;
     for (int w = 1; w <= kMaxGridWaves; ++w) {
         const size_t b = grid_lds_bytes(prec, W, T, Ms, w) + 256;
         if (b > kMaxLds) break;
         const int total = std::min(static_cast<int>(kMaxLds / b) * w, by_registers);
-        if (total > best_total) { best = w; best_total = total; }
+        if (total > best_total || (total == best_total && w <= prefer)) { best = w; best_total = total; }
     }
     return best;
 }

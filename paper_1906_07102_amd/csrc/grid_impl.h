@@ -70,26 +70,21 @@ struct AccF32 {
     };
 };
 
-// Compensated FP32 (Kahan). Registers hold (s, c) pairs per component with
-// value s - c. The flush adds s to the patch sum exactly (Knuth's TwoSum
-// gives the rounding error of that addition), and the error together with
-// the register compensation to the patch's compensation term. A cell's value
-// is sum + comp.
+// Compensated FP32 tile sums. A lane sums one piece (at most kPiece terms of
+// one cell) in plain FP32 registers, and each flush adds that sum to the
+// patch cell's (hi, lo) pair with TwoSum (Knuth: the rounding error of the
+// addition, exactly), which goes to lo. So the many flushes that reach a patch
+// cell, and the merges of patches, add no rounding error beyond the pieces'
+// own short sums. A cell's value is hi + lo. Two registers per tap (as FP32)
+// keep W = 7 in one pass over each piece.
 struct AccKahan {
-    using Cell = float4;      // (sum re, sum im, comp re, comp im)
-    using Reg = float4;       // (s re, s im, c re, c im)
+    using Cell = float4;      // (hi re, hi im, lo re, lo im)
+    using Reg = float2;
     __device__ static void zero_cell(Cell* c) { *c = make_float4(0.f, 0.f, 0.f, 0.f); }
-    __device__ static void kahan(float& s, float& c, float x) {
-        const float y = x - c;
-        const float t = s + y;
-        c = (t - s) - y;
-        s = t;
-    }
-    // the first term of a sum: what kahan() gives from zeros, without the zeros
-    __device__ static void set(Reg& r, float re, float im) { r = make_float4(re, im, 0.f, 0.f); }
+    __device__ static void set(Reg& r, float re, float im) { r = make_float2(re, im); }
     __device__ static void add(Reg& r, float re, float im) {
-        kahan(r.x, r.z, re);
-        kahan(r.y, r.w, im);
+        r.x += re;
+        r.y += im;
     }
     __device__ static void two_sum(float a, float b, float& s, float& e) {
         s = a + b;
@@ -104,7 +99,7 @@ struct AccKahan {
         two_sum(s.x, r.x, nx, ex);
         two_sum(s.y, r.y, ny, ey);
         lds_st(h, as_u64(make_float2(nx, ny)));
-        lds_st(h + 1, as_u64(make_float2(k.x + (ex - r.z), k.y + (ey - r.w))));
+        lds_st(h + 1, as_u64(make_float2(k.x + ex, k.y + ey)));
     }
     // Compensated sum of cells in FP32: the high parts are added with TwoSum, and their rounding errors
     // together with the cells' compensation terms go to the low part (value = hi + lo).
@@ -165,7 +160,7 @@ struct AccF64 {
 
 // Register accumulation: a lane sums one piece's contributions to a group of
 // RG footprint rows (RG x W accumulators) and then adds them to the patch;
-// wider footprints, or the two-register-per-value compensated and FP64
+// wider footprints, or the two-register-per-value FP64
 // accumulators, take several such passes over the piece so that the
 // accumulators stay within about kAccRegs registers (more waves fit).
 constexpr int kAccRegs = 112;
