@@ -87,13 +87,34 @@ __global__ __launch_bounds__(64 * kScanGroups) void k_plan_colscan(PlanGeom g, i
     const int len = b1 - b0;
     const int lo = b0 + static_cast<int>((static_cast<int64_t>(len) * grp) / kScanGroups);
     const int hi = b0 + static_cast<int>((static_cast<int64_t>(len) * (grp + 1)) / kScanGroups);
+    // Both passes take kU blocks' counts at a time, all loads issued before the first is used.
+    constexpr int kU = 8;
     int sum = 0;
-    for (int b = lo; b < hi; ++b) sum += blockhist[static_cast<size_t>(b) * hs + col];
+    int b = lo;
+    for (; b + kU <= hi; b += kU) {
+        int x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) x[u] = blockhist[static_cast<size_t>(b + u) * hs + col];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) sum += x[u];
+    }
+    for (; b < hi; ++b) sum += blockhist[static_cast<size_t>(b) * hs + col];
     part[grp][threadIdx.x & 63] = sum;
     __syncthreads();
     int run = 0;
     for (int q = 0; q < grp; ++q) run += part[q][threadIdx.x & 63];
-    for (int b = lo; b < hi; ++b) {
+    b = lo;
+    for (; b + kU <= hi; b += kU) {
+        int x[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) x[u] = blockhist[static_cast<size_t>(b + u) * hs + col];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            blockhist[static_cast<size_t>(b + u) * hs + col] = run;
+            run += x[u];
+        }
+    }
+    for (; b < hi; ++b) {
         int* p = blockhist + static_cast<size_t>(b) * hs + col;
         const int x = *p;
         *p = run;
