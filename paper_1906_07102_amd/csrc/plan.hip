@@ -5,6 +5,7 @@
 namespace lmg {
 namespace dev {
 
+
 // Set (never cleared by a kernel) when a plan meets non-finite coordinates;
 // read and cleared by lmg_sync_status through the runtime's symbol copies.
 __device__ int g_data_error;
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan_scatter(const double2* __
 #pragma unroll
         for (int u = 0; u < kB; ++u) {
             const int64_t k = base + i0 + u * kPlanThreads + threadIdx.x;
-            if (k < end) c[u] = uv[k];
+            if (k < end) c[u] = nt_load(uv + k);     // the coordinates' last read
         }
         int key[kB];                                         // tile slot (ntiles: dropped), -1 past the block
 #pragma unroll
@@ -355,6 +356,7 @@ constexpr int kPermThreads = 1024;     // (256 / 512 / 1024: place 123 / 123 / 1
 // valid visibilities (flags[2] of them; dropped ones sit above). Consecutive
 // workgroups take consecutive indices on one XCD, so its L2 sees one window
 // of the caller order at a time and merges the scattered writes into lines.
+
 template <typename R>
 __global__ __launch_bounds__(kPermThreads) void k_plan_place(const int* __restrict__ inv0,
                                                     const typename Pack<R>::T2* __restrict__ offk,
@@ -362,8 +364,8 @@ __global__ __launch_bounds__(kPermThreads) void k_plan_place(const int* __restri
                                                     typename Pack<R>::T2* __restrict__ off0) {
     const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
-    const int d = inv0[k];
-    if (d < flags[2]) off0[d] = offk[k];
+    const int d = nt_load(inv0 + k);
+    if (d < flags[2]) off0[d] = nt_load(offk + k);
 }
 
 // Pass 4 (workgroups loop over items): order the item's visibilities into
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(kPermThreads) void k_plan_compose(const int* __rest
 #pragma unroll
     for (int e = 0; e < kComposeE; ++e) {
         const int64_t k = base + e * blockDim.x;
-        d[e] = k < nvis ? inv0[k] : 0;               // 0: a valid position (nvis > 0), result unused
+        d[e] = k < nvis ? nt_load(inv0 + k) : 0;     // 0: a valid position (nvis > 0), result unused
     }
     int r[kComposeE];
 #pragma unroll
@@ -550,11 +552,11 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_in(const typename C2<R
                                                     typename C2<R>::T* __restrict__ vs) {
     const int64_t k = static_cast<int64_t>(xcd_chunk(blockIdx.x, gridDim.x)) * blockDim.x + threadIdx.x;
     if (k >= nvis) return;
-    const int d = inv[k];
+    const int d = nt_load(inv + k);
     if (d < 0) return;
-    typename C2<R>::T v = vis[k];
+    typename C2<R>::T v = nt_load(vis + k);
     if (w) {
-        const R wk = static_cast<R>(w[k]);
+        const R wk = static_cast<R>(nt_load(w + k));
         v.x *= wk;
         v.y *= wk;
     }
@@ -575,7 +577,7 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_out(const typename C2<
 #pragma unroll
     for (int e = 0; e < kPermOutE; ++e) {
         const int64_t k = base + e * blockDim.x;
-        d[e] = k < nvis ? inv[k] : -1;
+        d[e] = k < nvis ? nt_load(inv + k) : -1;
     }
     typename C2<R>::T v[kPermOutE];
 #pragma unroll
