@@ -26,14 +26,15 @@ hipError_t launch_grid(lmg_precision prec, const GridArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_assemble(lmg_precision prec, const AssembleArgs& args, hipStream_t s) {
-    // Rows of a tile per workgroup: 8 while the window has few tiles (the dense ones split over several
-    // workgroups, for balance); about 1,024 cells when it has many, as in a batched plan's full grids of
-    // mostly empty tiles, where smaller workgroups make the write bound by workgroup dispatch.
+    // Rows of a tile per workgroup: 16 while the window has few tiles (the dense ones split over two
+    // workgroups, for balance; the occupied band of a 4096^2 grid: 4 / 8 / 16 / 32 rows 56 / 36 / 33 / 43 us);
+    // about 1,024 cells when it has many, as in a batched plan's full grids of mostly empty tiles, where
+    // smaller workgroups make the write bound by workgroup dispatch.
     AssembleArgs a = args;
     // A whole grid of one channel (tiles of mostly empty cells) is also written whole tiles at a time.
     const int64_t tiles = static_cast<int64_t>(a.nchan) * a.trows * a.tcols;
     const bool whole_grid = a.trows == a.ntx && a.tcols == a.ntx && tiles >= 4096;
-    a.rows = (tiles > 32768 || whole_grid) ? std::min(a.T, 1024 / a.T) : std::min(a.T, 8);
+    a.rows = (tiles > 32768 || whole_grid) ? std::min(a.T, 1024 / a.T) : std::min(a.T, 16);
     // Whole grids of a batch: runs of grid rows, tile by tile (one cell of a tile per thread), while that
     // still makes at least 8,192 workgroups.
     a.rows_kernel = 0;
