@@ -19,9 +19,10 @@ namespace dev {
 //
 // A radix-8 stage has N/8 butterflies per row, so a two-row workgroup of
 // 1,024 threads transforms 4,096-point rows with one butterfly per thread and
-// four stages (eight barriers) instead of six radix-4 stages (twelve). The
-// four passes of a 4096^2 image take about 145 us against 177 us with radix
-// 4, and 165 us with one row per workgroup.
+// four stages (eight barriers) instead of six radix-4 stages (twelve). With
+// the same load and store phases, the four passes of a 4096^2 image took
+// about 145 us against 177 us with radix 4, and 165 us with one row per
+// workgroup (about 120 us once those phases issued their loads together).
 template <int N, int ROWS>
 struct FftShape {
     static constexpr int kLog2 = __builtin_ctz(N);
@@ -61,8 +62,8 @@ __device__ __forceinline__ void twiddle(const typename C2<R>::T* __restrict__ tw
 // fits. Rows hold one pad element after every 16 (ROW_PAD) when that still
 // fits: the first radix-8 stage stores each thread's eight outputs to
 // consecutive positions, so the lanes of a wave store 8 elements apart, into
-// few LDS banks, and the pad spreads them (four passes about 145 us against 153 us
-// unpadded).
+// few LDS banks, and the pad spreads them (four passes about 145 us against
+// 153 us unpadded, before the load phases were reordered).
 template <typename R, int N, int ROWS>
 struct FftLds {
     static constexpr size_t kEl = sizeof(typename C2<R>::T);
