@@ -85,14 +85,16 @@ def test_precision_study():
     assert err[(3, lmg.F64)] > err[(5, lmg.F64)] > err[(7, lmg.F64)]
 
 
-def test_compensated_accumulation_on_the_full_grid():
-    """Gridding 16.8M visibilities at W = 7: compensated FP32 against plain FP32, both against FP64."""
+@pytest.mark.parametrize("W", [5, 7])
+def test_compensated_accumulation_on_the_full_grid(W):
+    """Gridding 16.8M visibilities at W = 5 and 7 (the compensated form runs two and three waves per workgroup
+    there): compensated FP32 against plain FP32, both against FP64."""
     c, uv, vis64 = case()
-    otab, h = lt.make_table(7, c.x0, 300, 3)
-    tab = lmg.Table.from_nodes(7, c.x0, 300, 3, h, otab.nodes)
+    otab, h = lt.make_table(W, c.x0, 300, 3)
+    tab = lmg.Table.from_nodes(W, c.x0, 300, 3, h, otab.nodes)
     grids = {}
     for prec in (lmg.F32, lmg.F32_KAHAN, lmg.F64):
-        print(f"full grid prec={prec}", flush=True)
+        print(f"full grid W={W} prec={prec}", flush=True)
         plan = lmg.Plan(tab, c.N, uv, prec)
         vis = vis64.to(torch.complex128) if prec == lmg.F64 else vis64
         grids[prec] = plan.grid(vis).to(torch.complex128)
@@ -100,6 +102,6 @@ def test_compensated_accumulation_on_the_full_grid():
     nref = torch.linalg.vector_norm(ref).item()
     e32 = torch.linalg.vector_norm(grids[lmg.F32] - ref).item() / nref
     ek = torch.linalg.vector_norm(grids[lmg.F32_KAHAN] - ref).item() / nref
-    print(f"grid rel rms vs FP64: f32 {e32:.3e}  kahan {ek:.3e}", flush=True)
+    print(f"W={W} grid rel rms vs FP64: f32 {e32:.3e}  kahan {ek:.3e}", flush=True)
     assert ek < e32
     assert ek < 2.0 ** -24          # complex64 rounding of the result (relative RMS below the unit roundoff)
